@@ -344,6 +344,7 @@ int or_dacg(const prob *P, int m, const double *Qt, const double *x0, double tol
     double q = dot(n, x, Ax);
     double gamma_prev = 0.0;
     int it = 0;
+    for (int i = 0; i < n; i++) d[i] = 0.0; /* no previous direction: the first step is d = -h */
     for (; it < itmax; it++) {
         for (int i = 0; i < n; i++) g[i] = Ax[i] - q * x[i];
         if (nrm2(n, g) <= tol * q) break;

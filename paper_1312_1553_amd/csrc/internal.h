@@ -1,0 +1,184 @@
+// Internal declarations of the bnx library (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bnx {
+
+constexpr int kMaxP = 32;      // eigenpairs per solve
+constexpr int kMaxK = 16;      // BFGS window
+constexpr int kMaxQ = kMaxP + 1;
+constexpr int kMaxVec = 80;    // vectors in one kernel argument list
+constexpr int kNBMax = 2048;   // blocks of a streaming kernel (partials per dot)
+constexpr int kPartSlots = 80; // dots per partial area
+constexpr int kBlock = 256;
+
+// Pointer list passed by value to kernels.
+template <typename T>
+struct VList {
+  const T *p[kMaxVec];
+};
+
+// Scalars of the solve kept on the device (all in double).
+struct DevCtl {
+  // correction-equation PCG (Sec. 4.3)
+  double theta, rho, gamma, beta, g0, gn, pJp, q, xx, xAx, eigres, gc0;
+  double a[kMaxK], b[kMaxK], e[kMaxK], sig[kMaxK], rhoR[kMaxK];
+  double zy[kMaxQ], zQ[kMaxQ], Qg[kMaxQ], Qc0[kMaxQ], Qp[kMaxQ], Qr[kMaxQ];
+  double alpha[kMaxK];            // s_t^T r_t, chronological
+  double M[kMaxK * kMaxK];        // M[s*kMaxK+t] = s_s^T r_t
+  double QS[kMaxQ * kMaxK];       // QS[c*kMaxK+s] = q_c^T s_s
+  double tol_pcg, tau, xi;
+  int k, m, itmax, exit_rule, its, done, reason, first, eigtest;
+  // DACG (Sec. 4.1)
+  double dq, dxx, dxAx, dgamma, dgamma_prev, dalpha, dinv, dgn, dtol;
+  int dits, ddone, ditmax;
+  // outer step (always double)
+  double oz[kMaxQ], onrm2, otheta, orn, oalpha, osn2, ornold;
+  // backward
+  double bz[kMaxQ];
+  int err;  // bounded wait exceeded somewhere
+};
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Level schedule of a triangular factor.
+struct Levels {
+  int nlev = 0;
+  std::vector<int> ptr;   // nlev+1
+  std::vector<int> rows;  // n, rows sorted by level
+  int max_rows = 0;
+};
+
+// Host-side analysis of the CSR pattern (done once per context).
+struct Analysis {
+  int n = 0, nnz = 0, nnzL = 0;
+  std::vector<int> rp, ci;          // A
+  std::vector<int> Lrp, Lci, mapL;  // L rows (diag last), A position of each L entry
+  std::vector<int> Ltrp, Ltci, mapLt;  // L^T rows (diag first), L position of each L^T entry
+  Levels levL, levLt;
+};
+
+// Validate CSR; returns empty string if fine, else the problem.
+std::string validate_csr(int n, int nnz, const int *rp, const int *ci);
+// Build L / L^T patterns and level schedules.
+void analyse(Analysis &an);
+
+// ----------------------------------------------------------------- launchers
+int spmv_group(double mean_nnz);
+
+template <typename T>
+struct Mat {
+  int n = 0;
+  const int *rp = nullptr, *ci = nullptr;
+  const T *v = nullptr;
+  int group = 8;
+};
+
+template <typename T>
+struct Tri {
+  int n = 0;
+  const int *rp = nullptr, *ci = nullptr;
+  const T *v = nullptr;
+  const int *lev_rows = nullptr;
+  std::vector<int> lev_ptr;  // host copy for level launches
+  int nlev = 0;
+  bool lower = true;         // true: diag last (L); false: diag first (L^T)
+};
+
+// Optional HIP-event timing of the SpMV and triangular-solve launches.
+// Kernel ids: 0/1 SpMV fp64/fp32, 2/3 forward solve fp64/fp32, 4/5 backward solve fp64/fp32.
+struct Profiler {
+  static constexpr int kIds = 6;
+  bool on = false;
+  double ms[kIds] = {0};
+  long long count[kIds] = {0};
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(hipStream_t st, hipEvent_t *a) {
+    *a = get();
+    (void)hipEventRecord(*a, st);
+  }
+  void end(hipStream_t st, int id, hipEvent_t a) {
+    hipEvent_t b = get();
+    (void)hipEventRecord(b, st);
+    pending.push_back({id, a, b});
+  }
+  // call after the stream has been synchronised
+  void drain() {
+    for (auto &p : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        ms[p.id] += t;
+        count[p.id]++;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    drain();
+    for (int i = 0; i < kIds; i++) {
+      ms[i] = 0;
+      count[i] = 0;
+    }
+  }
+  ~Profiler() {
+    for (auto &p : pending) {
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct Launch {
+  Profiler *prof = nullptr;
+  hipStream_t st;
+  int nb;          // streaming blocks
+  DevCtl *ctl;
+  double *part;    // partial areas: area a at part + a*kPartSlots*kNBMax
+  int *counter;    // work counters for sync-free solves
+  int trsv_mode;
+  int sf_waves;    // persistent waves for sync-free solves
+};
+
+inline double *area(const Launch &L, int a) { return L.part + (size_t)a * kPartSlots * kNBMax; }
+
+template <typename T>
+int launch_spmv(const Launch &L, const Mat<T> &A, const T *x, T *y, int ndy, const VList<T> &ly, int ndx,
+                 const VList<T> &lx, double *part, const int *gate);
+template <typename T, typename Acc>
+int launch_multidot(const Launch &L, int n, int D, const VList<T> &X, const VList<T> &Y, double *part,
+                    const int *gate);
+int grid_for(size_t work, int nbmax);
+template <typename T>
+void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, const VList<T> &R,
+                 const double *coef, const int *gate);
+template <typename Tin, typename Tout>
+void launch_cast(hipStream_t st, size_t n, const Tin *in, Tout *out);
+template <typename T>
+void launch_fill(hipStream_t st, size_t n, T *x, T v);
+
+}  // namespace bnx

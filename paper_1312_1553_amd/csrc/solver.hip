@@ -1,0 +1,2066 @@
+// DACG-Newton driver (Alg. 2) and the C-ABI of the bnx library.
+//
+// One PCG iteration on the correction equation (Sec. 4.3, Sec. 3.2) is, on the
+// device, with no host round trip:
+//   trsv L  (rhs w = g - R a fused: first loop of Alg. 1)  ->  trsv L^T  ->
+//   multi-dot (R^T c0, Q^T c0, g^T c0)  ->  control: second-loop coefficients,
+//   CGS coefficients, rho, beta  ->  p = c0 - S(a+b) - Q z + beta p  ->
+//   SpMV ap = A p with dots (p^T ap, p^T p, Q^T ap, Q^T p)  ->  control: gamma  ->
+//   update s, g, t = A s with dots (||g||, eigen-residual terms, S^T g, Q^T g)  ->
+//   eigen-residual pass  ->  control: exit tests (i)-(iv), first-loop coefficients.
+// The two loops of Alg. 1 are evaluated in compact form: with sigma = S^T g and
+// M[s][t] = s_s^T r_t, the first loop gives a_s = (sigma_s - sum_{t>s} a_t M[s][t])/alpha_s
+// and, with rho_s = r_s^T c0, the second loop b_s = (rho_s - sum_{t<s} (a_t+b_t) M[t][s])/alpha_s;
+// both equal the sequential recursions in exact arithmetic.  The CGS projection
+// z = Q^T c uses Q^T c = Q^T c0 - (Q^T S)(a+b).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <string>
+#include <type_traits>
+
+#include "../../include/bnx.h"
+#include "internal.h"
+
+using namespace bnx;
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+struct HipError {
+  std::string msg;
+  explicit HipError(std::string m) : msg(std::move(m)) {}
+};
+struct ApiError {
+  bnx_status code;
+  std::string msg;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ============================================================== device helpers
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic reduction of D partial areas (part[d*nb + b]) into out[d], in a 256-thread block.
+__device__ void reduce_parts(const double *part, int nb, int D, double *out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = w; d < D; d += 4) {
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += part[(size_t)d * nb + b];
+    s = wsum(s);
+    if (lane == 0) out[d] = s;
+  }
+  __syncthreads();
+}
+
+template <typename T, int MAXD>
+__device__ __forceinline__ void bpart(T (&acc)[MAXD], int nd, double *part) {
+  __shared__ double red[4][MAXD];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < MAXD; d++)
+    if (d < nd) {
+      T s = wsum(acc[d]);
+      if (lane == 0) red[w][d] = (double)s;
+    }
+  __syncthreads();
+  if (threadIdx.x < nd)
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] +
+                                                          red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+#define GRIDLOOP(i, n) for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
+
+// First loop of Alg. 1 in compact form: a_s for s = k-1..0.
+__device__ void first_loop(DevCtl *c) {
+  for (int s = c->k - 1; s >= 0; s--) {
+    double v = c->sig[s];
+    for (int t = s + 1; t < c->k; t++) v -= c->a[t] * c->M[s * kMaxK + t];
+    c->a[s] = v / c->alpha[s];
+  }
+}
+
+// ============================================================== PCG kernels
+// g = sgn * (r - Q (Q^T r)), s = 0, t = 0; dots: g^T g, S_t^T g (k), Q_c^T g (m)
+template <typename T, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(int n, const DevCtl *c, double sgn, const T *r, int m, VList<T> Q,
+                                                     int k, VList<T> S, T *g, T *s, T *t, double *part) {
+  T acc[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; d++) acc[d] = T(0);
+  GRIDLOOP(i, n) {
+    T v = r[i];
+    for (int q = 0; q < m; q++) v -= (T)c->Qr[q] * Q.p[q][i];
+    v *= (T)sgn;
+    g[i] = v;
+    s[i] = T(0);
+    if (t) t[i] = T(0);
+    acc[0] += v * v;
+#pragma unroll
+    for (int d = 1; d < MAXD; d++) {
+      if (d <= k) acc[d] += S.p[d - 1][i] * v;
+      else if (d <= k + m) acc[d] += Q.p[d - 1 - k][i] * v;
+    }
+  }
+  bpart<T, MAXD>(acc, 1 + k + m, part);
+}
+
+// y = ap - theta p - Q zy;  s += gamma p;  g -= gamma y;  t += gamma ap
+// dots: g^T g, [x^T (Au + t), x^T x with x = u + s], S^T g (k), Q^T g (m)
+template <typename T, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(int n, const DevCtl *c, const T *ap, const T *p, int m,
+                                                       VList<T> Q, int k, VList<T> S, const T *u, const T *Au, T *s,
+                                                       T *g, T *t, double *part) {
+  if (c->done) return;
+  const T theta = (T)c->theta, gamma = (T)c->gamma;
+  const int eig = c->eigtest;
+  T acc[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; d++) acc[d] = T(0);
+  GRIDLOOP(i, n) {
+    const T api = ap[i], pi = p[i];
+    T y = api - theta * pi;
+    for (int q = 0; q < m; q++) y -= (T)c->zy[q] * Q.p[q][i];
+    const T si = s[i] + gamma * pi;
+    const T gi = g[i] - gamma * y;
+    s[i] = si;
+    g[i] = gi;
+    acc[0] += gi * gi;
+    if (eig) {
+      const T ti = t[i] + gamma * api;
+      t[i] = ti;
+      const T xi = u[i] + si;
+      acc[1] += xi * (Au[i] + ti);
+      acc[2] += xi * xi;
+    }
+#pragma unroll
+    for (int d = 3; d < MAXD; d++) {
+      if (d < 3 + k) acc[d] += S.p[d - 3][i] * gi;
+      else if (d < 3 + k + m) acc[d] += Q.p[d - 3 - k][i] * gi;
+    }
+  }
+  bpart<T, MAXD>(acc, 3 + k + m, part);
+}
+
+// sum_i (Au_i + t_i - q (u_i + s_i))^2
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_eigres(int n, const DevCtl *c, const T *u, const T *Au, const T *s,
+                                                       const T *t, double *part) {
+  if (c->done || !c->eigtest) return;
+  const T q = (T)c->q;
+  T acc[1] = {T(0)};
+  GRIDLOOP(i, n) {
+    const T d = Au[i] + t[i] - q * (u[i] + s[i]);
+    acc[0] += d * d;
+  }
+  bpart<T, 1>(acc, 1, part);
+}
+
+// p = c0 - sum_s e_s S_s - sum_q zQ_q Q_q + beta p    (beta = 0 on the first application)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, const T *c0, int k, VList<T> S, int m,
+                                                     VList<T> Q, T *p, int with_beta) {
+  if (c->done) return;
+  const T beta = (T)c->beta;
+  GRIDLOOP(i, n) {
+    T v = c0[i];
+    for (int s = 0; s < k; s++) v -= (T)c->e[s] * S.p[s][i];
+    for (int q = 0; q < m; q++) v -= (T)c->zQ[q] * Q.p[q][i];
+    if (with_beta) v += beta * p[i];
+    p[i] = v;
+  }
+}
+
+// ============================================================== PCG control kernels
+__global__ void c_pcg_setup(DevCtl *c, double theta, int k, int m, int itmax, double tol_pcg, double tau, int exit_rule,
+                            double xi, int eigtest) {
+  if (threadIdx.x) return;
+  c->theta = theta;
+  c->k = k;
+  c->m = m;
+  c->itmax = itmax;
+  c->tol_pcg = tol_pcg;
+  c->tau = tau;
+  c->exit_rule = exit_rule;
+  c->xi = xi;
+  c->eigtest = eigtest;
+  c->its = 0;
+  c->done = 0;
+  c->reason = 0;
+  c->first = 1;
+}
+
+__global__ void c_pcg_qr(DevCtl *c, const double *part, int nb, int m) {
+  __shared__ double red[kMaxQ];
+  reduce_parts(part, nb, m, red);
+  if (threadIdx.x < m) c->Qr[threadIdx.x] = red[threadIdx.x];
+}
+
+// after k_pcg_init: g0, sigma, Q^T g, first-loop coefficients
+__global__ void c_pcg_init(DevCtl *c, const double *part, int nb) {
+  __shared__ double red[1 + kMaxK + kMaxQ];
+  const int k = c->k, m = c->m;
+  reduce_parts(part, nb, 1 + k + m, red);
+  if (threadIdx.x) return;
+  c->gn = sqrt(red[0]);
+  c->g0 = c->gn;
+  for (int s = 0; s < k; s++) c->sig[s] = red[1 + s];
+  for (int q = 0; q < m; q++) c->Qg[q] = red[1 + k + q];
+  if (!(c->g0 > 0.0)) {  // zero right-hand side: s = 0 is the solution
+    c->done = 1;
+    c->reason = 1;
+    return;
+  }
+  first_loop(c);
+}
+
+// after the multi-dot (R^T c0 (k), Q^T c0 (m), g^T c0): second loop, CGS, rho, beta
+__global__ void c_pcg_beta(DevCtl *c, const double *part, int nb) {
+  if (c->done) return;
+  __shared__ double red[kMaxK + kMaxQ + 1];
+  const int k = c->k, m = c->m;
+  reduce_parts(part, nb, k + m + 1, red);
+  if (threadIdx.x) return;
+  for (int s = 0; s < k; s++) {
+    double v = red[s];
+    for (int t = 0; t < s; t++) v -= c->e[t] * c->M[t * kMaxK + s];
+    c->b[s] = v / c->alpha[s];
+    c->e[s] = c->a[s] + c->b[s];
+  }
+  double rho1 = red[k + m];  // g^T c0
+  for (int s = 0; s < k; s++) rho1 -= c->e[s] * c->sig[s];
+  for (int q = 0; q < m; q++) {
+    double z = red[k + q];
+    for (int s = 0; s < k; s++) z -= c->e[s] * c->QS[q * kMaxK + s];
+    c->zQ[q] = z;
+    rho1 -= z * c->Qg[q];
+  }
+  if (c->first) {
+    c->beta = 0.0;
+    c->first = 0;
+  } else {
+    c->beta = rho1 / c->rho;
+  }
+  c->rho = rho1;
+}
+
+// after SpMV: p^T ap, Q^T ap (m), p^T p, Q^T p (m)  ->  zy, p^T J p, gamma
+__global__ void c_pcg_gamma(DevCtl *c, const double *part, int nb) {
+  if (c->done) return;
+  __shared__ double red[2 * kMaxQ + 2];
+  const int m = c->m;
+  reduce_parts(part, nb, 2 * (m + 1), red);
+  if (threadIdx.x) return;
+  const double th = c->theta;
+  const double pap = red[0], pp = red[m + 1];
+  double pJp = pap - th * pp;
+  for (int q = 0; q < m; q++) {
+    const double qp = red[m + 2 + q];
+    c->zy[q] = red[1 + q] - th * qp;
+    c->Qp[q] = qp;
+    pJp -= qp * c->zy[q];
+  }
+  c->pJp = pJp;
+  if (!(pJp > 0.0)) {
+    c->done = 1;
+    c->reason = 4;
+    return;
+  }
+  c->gamma = c->rho / pJp;
+}
+
+// after k_pcg_update: ||g||, q, sigma, Q^T g
+__global__ void c_pcg_q(DevCtl *c, const double *part, int nb) {
+  if (c->done) return;
+  __shared__ double red[3 + kMaxK + kMaxQ];
+  const int k = c->k, m = c->m;
+  reduce_parts(part, nb, 3 + k + m, red);
+  if (threadIdx.x) return;
+  c->gn = sqrt(red[0]);
+  c->xAx = red[1];
+  c->xx = red[2];
+  c->q = (c->xx > 0.0) ? red[1] / red[2] : 0.0;
+  for (int s = 0; s < k; s++) c->sig[s] = red[3 + s];
+  for (int q = 0; q < m; q++) c->Qg[q] = red[3 + k + q];
+}
+
+// exit tests (Sec. 4.3) and, when continuing, first-loop coefficients
+__global__ void c_pcg_exit(DevCtl *c, const double *part, int nb) {
+  if (c->done) return;
+  __shared__ double red[1];
+  if (c->eigtest) reduce_parts(part, nb, 1, red);
+  if (threadIdx.x) return;
+  c->its++;
+  c->eigres = c->eigtest ? sqrt(red[0] / c->xx) : INFINITY;
+  int why = -1;
+  if (c->gn <= c->tol_pcg * c->g0) why = 1;
+  else if (c->eigtest && c->eigres < c->tau * c->q) why = 2;
+  else if (c->exit_rule == 1 && c->eigtest && c->gn <= c->xi * c->eigres) why = 3;
+  else if (c->its >= c->itmax) why = 0;
+  if (why >= 0) {
+    c->done = 1;
+    c->reason = why;
+    return;
+  }
+  first_loop(c);
+}
+
+// ============================================================== generic combination
+// out = cb0 * b0 + (cb1 ? *cb1 : 0) * b1 + sum_t lc[t] V_t  with cb0 = cb0c * (cb0d ? *cb0d : 1);
+// lc = sgn * coef[t] (coef from device);  dots of out with W (nd) into part.
+template <typename T, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_comb(int n, T *out, const T *b0, double cb0c, const double *cb0d, const T *b1,
+                                                 const double *cb1, int nt, VList<T> V, const double *coef, double sgn,
+                                                 int nd, VList<T> W, double *part, const int *gate) {
+  if (gate && *gate) return;
+  const T c0 = (T)(cb0c * (cb0d ? *cb0d : 1.0));
+  const T c1 = cb1 ? (T)(*cb1) : T(0);
+  T acc[MAXD > 0 ? MAXD : 1];
+#pragma unroll
+  for (int d = 0; d < (MAXD > 0 ? MAXD : 1); d++) acc[d] = T(0);
+  GRIDLOOP(i, n) {
+    T v = b0 ? c0 * b0[i] : T(0);
+    if (b1) v += c1 * b1[i];
+    for (int t = 0; t < nt; t++) v += (T)(sgn * coef[t]) * V.p[t][i];
+    out[i] = v;
+#pragma unroll
+    for (int d = 0; d < MAXD; d++)
+      if (d < nd) acc[d] += v * W.p[d][i];
+  }
+  if (MAXD > 0) bpart<T, (MAXD > 0 ? MAXD : 1)>(acc, nd, part);
+}
+
+// ============================================================== outer step (double)
+// x = u + s;  dots: Qt_c^T x (nq), x^T x, s^T r, s^T s
+template <typename T, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_outer_add(int n, const double *u, const T *s, const double *r, double *x,
+                                                      int nq, VList<double> Qt, double *part) {
+  double acc[MAXD];
+#pragma unroll
+  for (int d = 0; d < MAXD; d++) acc[d] = 0.0;
+  GRIDLOOP(i, n) {
+    const double si = (double)s[i];
+    const double xi = u[i] + si;
+    x[i] = xi;
+    acc[0] += xi * xi;
+    acc[1] += si * r[i];
+    acc[2] += si * si;
+#pragma unroll
+    for (int d = 3; d < MAXD; d++)
+      if (d < 3 + nq) acc[d] += Qt.p[d - 3][i] * xi;
+  }
+  bpart<double, MAXD>(acc, 3 + nq, part);
+}
+
+// r = Au - theta u; ||r||^2; mirrors of u, Au, r in T
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_outer_resid(int n, const DevCtl *c, const double *u, const double *Au,
+                                                        double *r, T *uT, T *AuT, T *rT, double *part) {
+  const double th = c->otheta;
+  double acc[1] = {0.0};
+  GRIDLOOP(i, n) {
+    const double ri = Au[i] - th * u[i];
+    r[i] = ri;
+    acc[0] += ri * ri;
+    if (uT) {
+      uT[i] = (T)u[i];
+      AuT[i] = (T)Au[i];
+      rT[i] = (T)ri;
+    }
+  }
+  bpart<double, 1>(acc, 1, part);
+}
+
+__global__ void c_reduce_to(double *dst, const double *part, int nb, int D) {
+  __shared__ double red[kPartSlots];
+  reduce_parts(part, nb, D, red);
+  if (threadIdx.x < D) dst[threadIdx.x] = red[threadIdx.x];
+}
+
+// after k_outer_add: oz = Qt^T x, ||x||^2, alpha = s^T r_old, ||s||^2
+__global__ void c_outer_add(DevCtl *c, const double *part, int nb, int nq) {
+  __shared__ double red[3 + kMaxQ];
+  reduce_parts(part, nb, 3 + nq, red);
+  if (threadIdx.x) return;
+  c->onrm2 = red[0];
+  c->oalpha = red[1];
+  c->osn2 = red[2];
+  for (int q = 0; q < nq; q++) c->oz[q] = red[3 + q];
+}
+
+// CGS coefficients of the next pass (dots of the previous comb) and the last norm
+__global__ void c_outer_cgs(DevCtl *c, const double *part, int nb, int nq, int with_norm) {
+  __shared__ double red[kMaxQ + 1];
+  reduce_parts(part, nb, nq + with_norm, red);
+  if (threadIdx.x) return;
+  for (int q = 0; q < nq; q++) c->oz[q] = red[q];
+  if (with_norm) c->onrm2 = red[nq];
+}
+
+__global__ void c_set(double *dst, double v) {
+  if (threadIdx.x == 0) *dst = v;
+}
+
+__global__ void c_inv_sqrt(DevCtl *c, const double *src, double *dst) {
+  if (threadIdx.x) return;
+  *dst = 1.0 / sqrt(*src);
+}
+
+__global__ void c_outer_theta(DevCtl *c, const double *part, int nb) {
+  __shared__ double red[1];
+  reduce_parts(part, nb, 1, red);
+  if (threadIdx.x == 0) c->otheta = red[0];
+}
+
+__global__ void c_outer_rn(DevCtl *c, const double *part, int nb) {
+  __shared__ double red[1];
+  reduce_parts(part, nb, 1, red);
+  if (threadIdx.x == 0) c->orn = sqrt(red[0]);
+}
+
+// Gram blocks of the BFGS pairs (double).  Dots in part, in order:
+//   if inserted: s_new^T r_t (t < k), s_t^T r_new (t < k-1), Qt_c^T s_new (c < nqt);   then u^T s_t (t < k).
+__global__ void c_gram(DevCtl *c, const double *part, int nb, int shift, int inserted, int k, int nqt) {
+  __shared__ double red[kPartSlots];
+  const int D = (inserted ? (k + (k - 1) + nqt) : 0) + k;
+  reduce_parts(part, nb, D, red);
+  if (threadIdx.x) return;
+  if (shift) {  // drop the oldest pair (index 0)
+    for (int s = 0; s + 1 < kMaxK; s++) {
+      c->alpha[s] = c->alpha[s + 1];
+      for (int t = 0; t + 1 < kMaxK; t++) c->M[s * kMaxK + t] = c->M[(s + 1) * kMaxK + t + 1];
+      for (int q = 0; q < kMaxQ; q++) c->QS[q * kMaxK + s] = c->QS[q * kMaxK + s + 1];
+    }
+  }
+  int o = 0;
+  if (inserted) {
+    const int kn = k - 1;
+    for (int t = 0; t < k; t++) c->M[kn * kMaxK + t] = red[o + t];
+    o += k;
+    for (int t = 0; t < kn; t++) c->M[t * kMaxK + kn] = red[o + t];
+    o += kn;
+    c->alpha[kn] = c->M[kn * kMaxK + kn];
+    for (int q = 0; q < nqt; q++) c->QS[q * kMaxK + kn] = red[o + q];
+    o += nqt;
+  }
+  for (int t = 0; t < k; t++) c->QS[nqt * kMaxK + t] = red[o + t];
+}
+
+// Gram blocks from scratch, rows row0..row0+nrows-1 of M (kind 0, s_s^T r_t) or of Q^T S (kind 1)
+__global__ void c_gram_rows(DevCtl *c, const double *part, int nb, int k, int kind, int row0, int nrows) {
+  __shared__ double red[kPartSlots];
+  reduce_parts(part, nb, nrows * k, red);
+  if (threadIdx.x) return;
+  for (int a = 0; a < nrows; a++)
+    for (int t = 0; t < k; t++) {
+      if (kind == 0) c->M[(row0 + a) * kMaxK + t] = red[a * k + t];
+      else c->QS[(row0 + a) * kMaxK + t] = red[a * k + t];
+    }
+  if (kind == 0)
+    for (int a = 0; a < nrows; a++) c->alpha[row0 + a] = c->M[(row0 + a) * kMaxK + row0 + a];
+}
+
+// first-loop coefficients from sigma = S^T g and Q^T g (standalone preconditioner apply)
+__global__ void c_prec_a(DevCtl *c, const double *part, int nb, int k, int m) {
+  __shared__ double red[kMaxK + kMaxQ];
+  reduce_parts(part, nb, k + m, red);
+  if (threadIdx.x) return;
+  c->k = k;
+  c->m = m;
+  c->done = 0;
+  c->first = 1;
+  for (int s = 0; s < k; s++) c->sig[s] = red[s];
+  for (int q = 0; q < m; q++) c->Qg[q] = red[k + q];
+  first_loop(c);
+}
+
+// ============================================================== DACG kernels (Sec. 4.1)
+// x = x' * inv, Ax = Ax' * inv (when inv != 0), g = Ax - q x with q = xAx/xx of the scaled vector
+// dots: x^T x, x^T Ax  (q is formed by the control kernel from the previous dots)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dacg_scale(int n, const DevCtl *c, T *x, T *Ax, double *part) {
+  if (c->ddone) return;
+  const T inv = (T)c->dinv;
+  T acc[2] = {T(0), T(0)};
+  GRIDLOOP(i, n) {
+    T xi = x[i], ai = Ax[i];
+    if (inv != T(0)) {
+      xi *= inv;
+      ai *= inv;
+      x[i] = xi;
+      Ax[i] = ai;
+    }
+    acc[0] += xi * xi;
+    acc[1] += xi * ai;
+  }
+  bpart<T, 2>(acc, 2, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, const T *x, const T *Ax, T *g,
+                                                      double *part) {
+  if (c->ddone) return;
+  const T q = (T)c->dq;
+  T acc[1] = {T(0)};
+  GRIDLOOP(i, n) {
+    const T gi = Ax[i] - q * x[i];
+    g[i] = gi;
+    acc[0] += gi * gi;
+  }
+  bpart<T, 1>(acc, 1, part);
+}
+
+__global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
+  if (c->ddone) return;
+  __shared__ double red[2];
+  reduce_parts(part, nb, 2, red);
+  if (threadIdx.x) return;
+  c->dxx = red[0];
+  c->dxAx = red[1];
+  c->dq = red[1] / red[0];
+}
+
+__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb) {
+  if (c->ddone) return;
+  __shared__ double red[1];
+  reduce_parts(part, nb, 1, red);
+  if (threadIdx.x) return;
+  c->dgn = sqrt(red[0] / c->dxx);
+  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax) c->ddone = 1;
+}
+
+// after multi-dot (Qt^T c0 (nq), g^T c0): zQ, gamma, beta
+__global__ void c_dacg_beta(DevCtl *c, const double *part, int nb, int nq) {
+  if (c->ddone) return;
+  __shared__ double red[kMaxQ + 1];
+  reduce_parts(part, nb, nq + 1, red);
+  if (threadIdx.x) return;
+  // gamma = g^T h with h = c0 - Qt zQ and g orthogonal to Qt up to rounding: g^T h = g^T c0 - (Qt^T g)^T zQ,
+  // the second term is formed from Qg (dots of g with Qt) stored by the previous multidot.
+  double gam = red[nq];
+  for (int q = 0; q < nq; q++) {
+    c->zQ[q] = red[q];
+    gam -= red[q] * c->Qg[q];
+  }
+  c->beta = (c->dits == 0 || c->dgamma_prev == 0.0) ? 0.0 : gam / c->dgamma_prev;
+  c->dgamma = gam;
+}
+
+__global__ void c_dacg_qg(DevCtl *c, const double *part, int nb, int nq) {
+  if (c->ddone) return;
+  __shared__ double red[kMaxQ];
+  reduce_parts(part, nb, nq, red);
+  if (threadIdx.x < nq) c->Qg[threadIdx.x] = red[threadIdx.x];
+}
+
+// after SpMV Ad = A d with dots [d^T Ad, x^T Ad] (y-list) and [d^T Ax, d^T x, d^T d] (x-list)
+__global__ void c_dacg_alpha(DevCtl *c, const double *part, int nb) {
+  if (c->ddone) return;
+  __shared__ double red[5];
+  reduce_parts(part, nb, 5, red);
+  if (threadIdx.x) return;
+  const double dAd = red[0], xAd = red[1], dAx = red[2], xd = red[3], dd = red[4];
+  const double xAx = c->dxAx, xx = c->dxx;
+  const double bA = 0.5 * (xAd + dAx);  // symmetric A: both equal d^T A x
+  // minimiser of q(x + a d): A2 a^2 + B2 a + C2 = 0 (closed form), the root with the smaller quotient
+  const double A2 = dAd * xd - bA * dd, B2 = dAd * xx - xAx * dd, C2 = bA * xx - xAx * xd;
+  double r1, r2;
+  if (A2 == 0.0) {
+    r1 = r2 = (B2 != 0.0) ? -C2 / B2 : 0.0;
+  } else {
+    double disc = B2 * B2 - 4.0 * A2 * C2;
+    if (disc < 0.0) disc = 0.0;
+    const double tq = -0.5 * (B2 + (B2 >= 0.0 ? 1.0 : -1.0) * sqrt(disc));
+    r1 = tq / A2;
+    r2 = (tq != 0.0) ? C2 / tq : r1;
+  }
+  const double q1 = (xAx + 2 * r1 * bA + r1 * r1 * dAd) / (xx + 2 * r1 * xd + r1 * r1 * dd);
+  const double q2 = (xAx + 2 * r2 * bA + r2 * r2 * dAd) / (xx + 2 * r2 * xd + r2 * r2 * dd);
+  c->dalpha = (q2 < q1) ? r2 : r1;
+}
+
+// x += a d, Ax += a Ad; dots ||x||^2 (for the next scale)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dacg_step(int n, const DevCtl *c, T *x, T *Ax, const T *d, const T *Ad,
+                                                      double *part) {
+  if (c->ddone) return;
+  const T a = (T)c->dalpha;
+  T acc[1] = {T(0)};
+  GRIDLOOP(i, n) {
+    const T xi = x[i] + a * d[i];
+    x[i] = xi;
+    Ax[i] += a * Ad[i];
+    acc[0] += xi * xi;
+  }
+  bpart<T, 1>(acc, 1, part);
+}
+
+__global__ void c_dacg_next(DevCtl *c, const double *part, int nb) {
+  if (c->ddone) return;
+  __shared__ double red[1];
+  reduce_parts(part, nb, 1, red);
+  if (threadIdx.x) return;
+  c->dinv = 1.0 / sqrt(red[0]);
+  c->dgamma_prev = c->dgamma;
+  c->dits++;
+}
+
+__global__ void c_dacg_setup(DevCtl *c, double tol, int itmax) {
+  if (threadIdx.x) return;
+  c->dtol = tol;
+  c->ditmax = itmax;
+  c->dits = 0;
+  c->ddone = 0;
+  c->dinv = 0.0;
+  c->dgamma_prev = 0.0;
+}
+
+// ============================================================== IC(0) factor (device, level by level)
+__global__ void k_ic0_gather(int nnzL, const int *map, const double *val, double *Lv) {
+  GRIDLOOP(q, nnzL) Lv[q] = val[map[q]];
+}
+
+// rows of one level: L_ij = (A_ij - sum_{m<j} L_im L_jm)/L_jj ; L_ii = sqrt((1+a) A_ii - sum L_im^2)
+__global__ void k_ic0_level(int r0, int r1, const int *rows, const int *Lrp, const int *Lci, double *Lv, double shift,
+                            int *fail) {
+  const int pos = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= r1) return;
+  const int i = rows[pos];
+  const int e0 = Lrp[i], ed = Lrp[i + 1] - 1;
+  double dsum = 0.0;
+  for (int e = e0; e < ed; e++) {
+    const int j = Lci[e];
+    double s = Lv[e];
+    int p = e0, q = Lrp[j];
+    const int qend = Lrp[j + 1] - 1;
+    while (p < e && q < qend) {
+      const int cp = Lci[p], cq = Lci[q];
+      if (cp == cq) {
+        s -= Lv[p] * Lv[q];
+        p++;
+        q++;
+      } else if (cp < cq) {
+        p++;
+      } else {
+        q++;
+      }
+    }
+    s /= Lv[qend];
+    Lv[e] = s;
+    dsum += s * s;
+  }
+  const double d = Lv[ed] * (1.0 + shift) - dsum;
+  if (!(d > 0.0)) {
+    atomicOr(fail, 1);
+    Lv[ed] = 1.0;
+  } else {
+    Lv[ed] = sqrt(d);
+  }
+}
+
+__global__ void k_gather_d(int n, const int *map, const double *src, double *dst) {
+  GRIDLOOP(q, n) dst[q] = src[map[q]];
+}
+
+// ============================================================== output helpers
+__global__ void k_absmax(int n, const double *v, double *part) {
+  double m = 0.0;
+  GRIDLOOP(i, n) m = fmax(m, fabs(v[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// sign of the first entry with |v_i| > 1e-12 max|v| (per block: smallest such index, encoded with its sign)
+__global__ void k_firstbig(int n, const double *v, const double *part_max, int nbm, double *part) {
+  __shared__ double vmax_s;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int b = 0; b < nbm; b++) m = fmax(m, part_max[b]);
+    vmax_s = m;
+  }
+  __syncthreads();
+  const double thr = 1e-12 * vmax_s;
+  long long best = (long long)n;
+  GRIDLOOP(i, n) if (fabs(v[i]) > thr && i < best) best = i;
+  for (int off = 32; off > 0; off >>= 1) {
+    long long o = __shfl_xor(best, off, 64);
+    best = o < best ? o : best;
+  }
+  __shared__ long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long b = red[0];
+    for (int w = 1; w < 4; w++) b = red[w] < b ? red[w] : b;
+    part[blockIdx.x] = (double)b;
+  }
+}
+
+__global__ void k_sign_copy(int n, const double *v, const double *part_idx, int nb, double *out) {
+  __shared__ double sg;
+  if (threadIdx.x == 0) {
+    double b = (double)n;
+    for (int k = 0; k < nb; k++) b = fmin(b, part_idx[k]);
+    const long long i = (long long)b;
+    sg = (i < n && v[i] < 0.0) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  GRIDLOOP(i, n) out[i] = sg * v[i];
+}
+
+// ============================================================== backward kernels
+// g_vals[e=(a,b)] += sum_i ge_i v_i[a] v_i[b]
+__global__ void k_grad_lambda(int n, const int *rp, const int *ci, int p, const double *V, const double *ge,
+                              double *gv) {
+  GRIDLOOP(a, n) {
+    for (int e = rp[a]; e < rp[a + 1]; e++) {
+      const int b = ci[e];
+      double s = 0.0;
+      for (int i = 0; i < p; i++) s += ge[i] * V[(size_t)i * n + a] * V[(size_t)i * n + b];
+      gv[e] += s;
+    }
+  }
+}
+
+// g_vals[e=(a,b)] -= 1/2 (xi[a] v[b] + v[a] xi[b])
+__global__ void k_grad_vec(int n, const int *rp, const int *ci, const double *v, const double *xi, double *gv) {
+  GRIDLOOP(a, n) {
+    const double xa = xi[a], va = v[a];
+    for (int e = rp[a]; e < rp[a + 1]; e++) {
+      const int b = ci[e];
+      gv[e] -= 0.5 * (xa * v[b] + va * xi[b]);
+    }
+  }
+}
+
+// coefficients (v_j^T G)/(lambda_j - lambda_i) for j < i, from the dots in part
+__global__ void c_adj_coef(DevCtl *c, const double *part, int nb, int ni, const double *lam, int i) {
+  __shared__ double red[kMaxQ];
+  reduce_parts(part, nb, ni, red);
+  if (threadIdx.x < ni) c->bz[threadIdx.x] = red[threadIdx.x] / (lam[threadIdx.x] - lam[i]);
+}
+
+}  // namespace
+
+// ================================================================== context
+struct bnx_ctx {
+  int n = 0, nnz = 0, device_ptrs = 0;
+  hipStream_t st = nullptr;
+  std::string err;
+  Analysis an;
+  int group = 8;
+  // device arrays
+  int *rp = nullptr, *ci = nullptr;
+  double *val = nullptr;
+  float *val32 = nullptr;
+  int *Lrp = nullptr, *Lci = nullptr, *mapL = nullptr, *Ltrp = nullptr, *Ltci = nullptr, *mapLt = nullptr;
+  int *levL = nullptr, *levLt = nullptr;
+  double *Lv = nullptr, *Ltv = nullptr;
+  float *Lv32 = nullptr, *Ltv32 = nullptr;
+  DevCtl *ctl = nullptr;
+  DevCtl *hctl = nullptr;  // pinned readback
+  double *part = nullptr;
+  int *counter = nullptr;
+  int *dflag = nullptr;    // device int scratch
+  int *hflag = nullptr;    // pinned
+  bool factored = false, solved = false;
+  double shift_used = 0.0, t_factor = 0.0;
+  int trsv_mode = 0, sf_waves = 2048;
+  double adj_tol = 1e-12;
+  int adj_itmax = 2000;
+  // last solve
+  int p_last = 0;
+  std::vector<double> evals_last;
+  double *evecs_last = nullptr;  // n x p fp64 (sorted, signed)
+  int prec_last = 0;
+  std::vector<void *> owned;
+  Profiler prof;
+
+  template <typename T>
+  T *alloc(size_t count) {
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) throw ApiError{BNX_E_NOMEM, "device allocation failed"};
+    owned.push_back(q);
+    return static_cast<T *>(q);
+  }
+  void release(void *q) {
+    if (!q) return;
+    auto it = std::find(owned.begin(), owned.end(), q);
+    if (it != owned.end()) owned.erase(it);
+    (void)hipFree(q);
+  }
+  ~bnx_ctx() {
+    (void)hipStreamSynchronize(st);
+    for (void *q : owned) (void)hipFree(q);
+    if (hctl) (void)hipHostFree(hctl);
+    if (hflag) (void)hipHostFree(hflag);
+  }
+
+  Launch launch() const {
+    Launch L;
+    L.prof = const_cast<Profiler *>(&prof);
+    L.st = st;
+    L.nb = kNBMax;
+    L.ctl = ctl;
+    L.part = part;
+    L.counter = counter;
+    L.trsv_mode = trsv_mode;
+    L.sf_waves = sf_waves;
+    return L;
+  }
+  template <typename T>
+  Mat<T> mat() const;
+  template <typename T>
+  Tri<T> tri(bool lower) const;
+  void sync() {
+    HIPCHK(hipStreamSynchronize(st));
+    if (prof.on) prof.drain();
+  }
+  DevCtl readctl() {
+    HIPCHK(hipMemcpyAsync(hctl, ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, st));
+    sync();
+    return *hctl;
+  }
+};
+
+template <>
+Mat<double> bnx_ctx::mat<double>() const {
+  Mat<double> M;
+  M.n = n;
+  M.rp = rp;
+  M.ci = ci;
+  M.v = val;
+  M.group = group;
+  return M;
+}
+template <>
+Mat<float> bnx_ctx::mat<float>() const {
+  Mat<float> M;
+  M.n = n;
+  M.rp = rp;
+  M.ci = ci;
+  M.v = val32;
+  M.group = group;
+  return M;
+}
+template <>
+Tri<double> bnx_ctx::tri<double>(bool lower) const {
+  Tri<double> F;
+  F.n = n;
+  F.lower = lower;
+  F.rp = lower ? Lrp : Ltrp;
+  F.ci = lower ? Lci : Ltci;
+  F.v = lower ? Lv : Ltv;
+  F.lev_rows = lower ? levL : levLt;
+  const Levels &lv = lower ? an.levL : an.levLt;
+  F.lev_ptr = lv.ptr;
+  F.nlev = lv.nlev;
+  return F;
+}
+template <>
+Tri<float> bnx_ctx::tri<float>(bool lower) const {
+  Tri<float> F;
+  F.n = n;
+  F.lower = lower;
+  F.rp = lower ? Lrp : Ltrp;
+  F.ci = lower ? Lci : Ltci;
+  F.v = lower ? Lv32 : Ltv32;
+  F.lev_rows = lower ? levL : levLt;
+  const Levels &lv = lower ? an.levL : an.levLt;
+  F.lev_ptr = lv.ptr;
+  F.nlev = lv.nlev;
+  return F;
+}
+
+namespace {
+
+int gridn(int n) { return grid_for((size_t)n, kNBMax); }
+
+template <typename T>
+VList<T> vl(std::initializer_list<const T *> ps) {
+  VList<T> v{};
+  int i = 0;
+  for (const T *q : ps) v.p[i++] = q;
+  return v;
+}
+
+// ------------------------------------------------------------------ generic comb launcher
+template <typename T>
+int comb(bnx_ctx *C, T *out, const T *b0, double cb0c, const double *cb0d, const T *b1, const double *cb1, int nt,
+         const VList<T> &V, const double *coef, double sgn, int nd, const VList<T> &W, double *part,
+         const int *gate) {
+  const int nb = gridn(C->n);
+  if (nd == 0)
+    hipLaunchKernelGGL((k_comb<T, 0>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1, nt, V,
+                       coef, sgn, 0, W, part, gate);
+  else if (nd <= 2)
+    hipLaunchKernelGGL((k_comb<T, 2>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1, nt, V,
+                       coef, sgn, nd, W, part, gate);
+  else
+    hipLaunchKernelGGL((k_comb<T, kMaxQ + 1>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1,
+                       nt, V, coef, sgn, nd, W, part, gate);
+  return nb;
+}
+
+// ------------------------------------------------------------------ workspace
+template <typename T>
+struct Work {
+  int n = 0, kmax = 0, pcap = 0;
+  T *p, *ap, *s, *g, *t, *c0, *z, *u, *Au, *r, *x, *Ax, *d, *Ad, *dg;
+  T *S[kMaxK], *R[kMaxK];
+  T *Qm;  // n x pcap mirror of converged vectors
+};
+
+template <typename T>
+void make_work(bnx_ctx *C, Work<T> &w, int kmax, int pcap) {
+  const size_t n = C->n;
+  w.n = C->n;
+  w.kmax = kmax;
+  w.pcap = pcap;
+  T **vecs[] = {&w.p, &w.ap, &w.s, &w.g, &w.t, &w.c0, &w.z, &w.u, &w.Au, &w.r, &w.x, &w.Ax, &w.d, &w.Ad, &w.dg};
+  for (T **v : vecs) *v = C->alloc<T>(n);
+  for (int s = 0; s < kMaxK; s++) w.S[s] = w.R[s] = nullptr;
+  for (int s = 0; s < kmax; s++) {
+    w.S[s] = C->alloc<T>(n);
+    w.R[s] = C->alloc<T>(n);
+  }
+  w.Qm = C->alloc<T>(n * (size_t)std::max(pcap, 1));
+}
+
+template <typename T>
+void free_work(bnx_ctx *C, Work<T> &w) {
+  T *vecs[] = {w.p, w.ap, w.s, w.g, w.t, w.c0, w.z, w.u, w.Au, w.r, w.x, w.Ax, w.d, w.Ad, w.dg, w.Qm};
+  for (T *v : vecs) C->release(v);
+  for (int s = 0; s < w.kmax; s++) {
+    C->release(w.S[s]);
+    C->release(w.R[s]);
+  }
+}
+
+// ------------------------------------------------------------------ lagged done-flag polling
+// The host enqueues iteration l+1 before reading the flag written by iteration l.
+struct Poll {
+  bnx_ctx *C;
+  hipEvent_t ev[2];
+  int slot = 0;
+  explicit Poll(bnx_ctx *c) : C(c) {
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  }
+  ~Poll() {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
+  void post(const int *dflag_src) {
+    HIPCHK(hipMemcpyAsync(C->hflag + slot, dflag_src, sizeof(int), hipMemcpyDeviceToHost, C->st));
+    HIPCHK(hipEventRecord(ev[slot], C->st));
+    slot ^= 1;
+  }
+  // read the flag posted before the last post
+  int read_prev() {
+    const int s = slot;  // the older of the two slots
+    HIPCHK(hipEventSynchronize(ev[s]));
+    return C->hflag[s];
+  }
+};
+
+// ------------------------------------------------------------------ PCG on the correction equation
+struct PcgParams {
+  double theta = 0, tol_pcg = 1e-2, tau = 1e-8, xi = 0.1, sgn = -1.0;
+  int itmax = 20, exit_rule = 1, eigtest = 1;
+};
+
+// Solves J s = sgn (I - QQ^T) r with J = (I-QQ^T)(A - theta I)(I-QQ^T); Q = m vectors; pairs S,R (k,
+// chronological; Gram blocks already in ctl).  u, Au: for the eigen-residual test (eigtest).
+template <typename T>
+void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VList<T> &Q, int k, const VList<T> &S,
+         const VList<T> &R, const T *u, const T *Au, T *s_out, int *its, int *reason) {
+  const Launch L = C->launch();
+  const int n = C->n;
+  const int *gate = &C->ctl->done;
+  DevCtl *c = C->ctl;
+  Mat<T> A = C->mat<T>();
+  Tri<T> Lf = C->tri<T>(true), Lt = C->tri<T>(false);
+  hipLaunchKernelGGL(c_pcg_setup, dim3(1), dim3(64), 0, C->st, c, P.theta, k, m, P.itmax, P.tol_pcg, P.tau,
+                     P.exit_rule, P.xi, P.eigtest);
+  // Q^T r
+  if (m > 0) {
+    VList<T> rr{};
+    for (int q = 0; q < m; q++) rr.p[q] = r;
+    const int nb = launch_multidot<T, T>(L, n, m, Q, rr, area(L, 3), nullptr);
+    hipLaunchKernelGGL(c_pcg_qr, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nb, m);
+  }
+  const int nbi = gridn(n);
+  const int Di = 1 + k + m;
+  T *t = P.eigtest ? w.t : nullptr;
+  if (Di <= 8)
+    hipLaunchKernelGGL((k_pcg_init<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, P.sgn, r, m, Q, k, S, w.g, s_out,
+                       t, area(L, 1));
+  else
+    hipLaunchKernelGGL((k_pcg_init<T, 1 + kMaxK + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, P.sgn, r, m, Q,
+                       k, S, w.g, s_out, t, area(L, 1));
+  hipLaunchKernelGGL(c_pcg_init, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
+
+  VList<T> ly{}, lx{};
+  ly.p[0] = w.p;
+  lx.p[0] = w.p;
+  for (int q = 0; q < m; q++) ly.p[1 + q] = lx.p[1 + q] = Q.p[q];
+  VList<T> mdX{}, mdY{};
+  for (int s = 0; s < k; s++) {
+    mdX.p[s] = R.p[s];
+    mdY.p[s] = w.c0;
+  }
+  for (int q = 0; q < m; q++) {
+    mdX.p[k + q] = Q.p[q];
+    mdY.p[k + q] = w.c0;
+  }
+  mdX.p[k + m] = w.g;
+  mdY.p[k + m] = w.c0;
+  const int Du = 3 + k + m;
+
+  Poll poll(C);
+  int l;
+  for (l = 0; l <= P.itmax; l++) {
+    // c0 = P0^ (g - R a)   (first loop fused into the forward solve)
+    launch_trsv<T>(L, Lf, w.g, w.z, k, R, c->a, gate);
+    launch_trsv<T>(L, Lt, w.z, w.c0, 0, R, nullptr, gate);
+    int nbd = launch_multidot<T, T>(L, n, k + m + 1, mdX, mdY, area(L, 3), gate);
+    hipLaunchKernelGGL(c_pcg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd);
+    hipLaunchKernelGGL((k_pcg_newp<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p, l > 0 ? 1 : 0);
+    // y = J p
+    int nbs = launch_spmv<T>(L, A, w.p, w.ap, m + 1, ly, m + 1, lx, area(L, 0), gate);
+    hipLaunchKernelGGL(c_pcg_gamma, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbs);
+    if (Du <= 8)
+      hipLaunchKernelGGL((k_pcg_update<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u, Au,
+                         s_out, w.g, t, area(L, 1));
+    else
+      hipLaunchKernelGGL((k_pcg_update<T, 3 + kMaxK + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m,
+                         Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
+    hipLaunchKernelGGL(c_pcg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
+    hipLaunchKernelGGL((k_pcg_eigres<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, s_out, t, area(L, 2));
+    hipLaunchKernelGGL(c_pcg_exit, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbi);
+    poll.post(gate);
+    if (l > 0 && poll.read_prev()) break;
+  }
+  DevCtl h = C->readctl();
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  *its = h.its;
+  *reason = h.reason;
+}
+
+// ------------------------------------------------------------------ double-precision helpers
+// x <- x - Q (Q^T x) twice, then x <- x/||x||   (Q: nq columns, double)
+void cgs2_normalize(bnx_ctx *C, double *x, double *tmp, int nq, const VList<double> &Q) {
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const int n = C->n;
+  VList<double> X{}, Y{};
+  for (int q = 0; q < nq; q++) {
+    X.p[q] = Q.p[q];
+    Y.p[q] = x;
+  }
+  for (int pass = 0; pass < 2 && nq > 0; pass++) {
+    int nb = launch_multidot<double, double>(L, n, nq, X, Y, area(L, 4), nullptr);
+    hipLaunchKernelGGL(c_outer_cgs, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb, nq, 0);
+    comb<double>(C, tmp, x, 1.0, nullptr, nullptr, nullptr, nq, Q, c->oz, -1.0, 0, VList<double>{}, nullptr, nullptr);
+    HIPCHK(hipMemcpyAsync(x, tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+  }
+  VList<double> W = vl<double>({x});
+  int nb = launch_multidot<double, double>(L, n, 1, W, W, area(L, 4), nullptr);
+  hipLaunchKernelGGL(c_outer_cgs, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb, 0, 1);
+  hipLaunchKernelGGL(c_inv_sqrt, dim3(1), dim3(1), 0, C->st, c, &c->onrm2, &c->dinv);
+  comb<double>(C, tmp, x, 1.0, &c->dinv, nullptr, nullptr, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+               nullptr, nullptr);
+  HIPCHK(hipMemcpyAsync(x, tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+}
+
+// Au = A u, theta = u^T A u, r = Au - theta u, ||r||; mirrors in T (when uT != nullptr)
+template <typename T>
+void outer_eval(bnx_ctx *C, const double *u, double *Au, double *r, T *uT, T *AuT, T *rT) {
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const int n = C->n;
+  Mat<double> A = C->mat<double>();
+  VList<double> ly = vl<double>({u});
+  int nb = launch_spmv<double>(L, A, u, Au, 1, ly, 0, VList<double>{}, area(L, 5), nullptr);
+  hipLaunchKernelGGL(c_outer_theta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nb);
+  const int nbi = gridn(n);
+  hipLaunchKernelGGL((k_outer_resid<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, r, uT, AuT, rT, area(L, 5));
+  hipLaunchKernelGGL(c_outer_rn, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
+}
+
+// ------------------------------------------------------------------ DACG (Sec. 4.1)
+// x (T) holds the normalised start vector; on return x is the DACG iterate (unit norm).
+template <typename T>
+int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itmax, long long *mvp) {
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const int n = C->n;
+  const int *gate = &c->ddone;
+  Mat<T> A = C->mat<T>();
+  Tri<T> Lf = C->tri<T>(true), Lt = C->tri<T>(false);
+  const int nbi = gridn(n);
+  hipLaunchKernelGGL(c_dacg_setup, dim3(1), dim3(64), 0, C->st, c, tol, itmax);
+  launch_fill<T>(C->st, n, w.d, T(0));  // no previous direction: the first step is d = -h
+  // Ax
+  launch_spmv<T>(L, A, w.x, w.Ax, 0, VList<T>{}, 0, VList<T>{}, nullptr, nullptr);
+  (*mvp)++;
+  VList<T> mdX{}, mdY{}, mdQg{}, mdQgY{};
+  for (int q = 0; q < nq; q++) {
+    mdX.p[q] = Qt.p[q];
+    mdY.p[q] = w.c0;
+    mdQg.p[q] = Qt.p[q];
+    mdQgY.p[q] = w.dg;
+  }
+  mdX.p[nq] = w.dg;
+  mdY.p[nq] = w.c0;
+  VList<T> ly{}, lx{};
+  ly.p[0] = w.d;
+  ly.p[1] = w.x;
+  lx.p[0] = w.Ax;
+  lx.p[1] = w.x;
+  lx.p[2] = w.d;
+  Poll poll(C);
+  int it;
+  for (it = 0; it <= itmax; it++) {
+    hipLaunchKernelGGL((k_dacg_scale<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, area(L, 0));
+    hipLaunchKernelGGL(c_dacg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbi);
+    hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
+    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
+    // h = (I - Qt Qt^T) P0^ g
+    launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
+    launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
+    if (nq > 0) {
+      int nbq = launch_multidot<T, T>(L, n, nq, mdQg, mdQgY, area(L, 2), gate);
+      hipLaunchKernelGGL(c_dacg_qg, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbq, nq);
+    }
+    int nbd = launch_multidot<T, T>(L, n, nq + 1, mdX, mdY, area(L, 3), gate);
+    hipLaunchKernelGGL(c_dacg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd, nq);
+    // d = -(c0 - Qt zQ) + beta d
+    comb<T>(C, w.d, w.c0, -1.0, nullptr, w.d, &c->beta, nq, Qt, c->zQ, 1.0, 0, VList<T>{}, nullptr, gate);
+    int nbs = launch_spmv<T>(L, A, w.d, w.Ad, 2, ly, 3, lx, area(L, 4), gate);
+    hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs);
+    hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, area(L, 5));
+    hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
+    poll.post(gate);
+    if (it > 0 && poll.read_prev()) break;
+  }
+  DevCtl h = C->readctl();
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  // the last (gated) scale of x was skipped after convergence: x holds the scaled iterate
+  *mvp += h.dits;
+  return h.dits;
+}
+
+// ------------------------------------------------------------------ Gram blocks from scratch
+template <typename T>
+void gram_full(bnx_ctx *C, int k, const VList<T> &S, const VList<T> &R, int m, const VList<T> &Q) {
+  const Launch L = C->launch();
+  const int n = C->n;
+  if (k == 0) return;
+  const int rows_per = kMaxVec / k;
+  for (int kind = 0; kind < 2; kind++) {
+    const int nrows_all = kind == 0 ? k : m;
+    for (int r0 = 0; r0 < nrows_all; r0 += rows_per) {
+      const int nr = std::min(rows_per, nrows_all - r0);
+      VList<T> X{}, Y{};
+      int D = 0;
+      for (int a = 0; a < nr; a++)
+        for (int t = 0; t < k; t++) {
+          X.p[D] = kind == 0 ? S.p[r0 + a] : Q.p[r0 + a];
+          Y.p[D++] = kind == 0 ? R.p[t] : S.p[t];
+        }
+      const int nb = launch_multidot<T, double>(L, n, D, X, Y, area(L, 6), nullptr);
+      hipLaunchKernelGGL(c_gram_rows, dim3(1), dim3(kBlock), 0, C->st, C->ctl, area(L, 6), nb, k, kind, r0, nr);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ splitmix64 start block
+__global__ void k_splitmix(size_t count, uint64_t seed, double *out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    out[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+// ------------------------------------------------------------------ full solve (Alg. 2)
+template <typename T>
+bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double *evecs, bnx_stats *st) {
+  const int n = C->n, p = o.p;
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const bool fp64 = std::is_same<T, double>::value;
+  Work<T> w;
+  make_work<T>(C, w, o.kmax, p);
+  struct Guard {
+    bnx_ctx *C;
+    Work<T> *w;
+    std::vector<double *> extra;
+    ~Guard() {
+      free_work<T>(C, *w);
+      for (double *q : extra) C->release(q);
+    }
+  } guard{C, &w, {}};
+  auto dalloc = [&](size_t cnt) {
+    double *q = C->alloc<double>(cnt);
+    guard.extra.push_back(q);
+    return q;
+  };
+  double *V64 = dalloc((size_t)n * p);  // converged vectors v_1..v_p (unsorted)
+  double *X0 = dalloc((size_t)n * p);
+  double *u = dalloc(n), *Au = dalloc(n), *rA = dalloc(n), *rB = dalloc(n), *x64 = dalloc(n), *tmp = dalloc(n);
+  if (o.x0) {
+    HIPCHK(hipMemcpyAsync(X0, o.x0, sizeof(double) * n * p, C->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          C->st));
+  } else {
+    hipLaunchKernelGGL(k_splitmix, dim3(1024), dim3(kBlock), 0, C->st, (size_t)n * p, (uint64_t)o.seed, X0);
+  }
+  std::vector<double> lam(p);
+  bnx_stats S{};
+  double t0;
+  for (int j = 0; j < p; j++) {
+    // ---- start vector orthogonal to v_1..v_{j-1} and DACG (Sec. 4.1)
+    t0 = now_s();
+    VList<double> Qt64{};
+    VList<T> QtT{};
+    for (int q = 0; q < j; q++) {
+      Qt64.p[q] = V64 + (size_t)q * n;
+      QtT.p[q] = fp64 ? (const T *)(V64 + (size_t)q * n) : w.Qm + (size_t)q * n;
+    }
+    HIPCHK(hipMemcpyAsync(x64, X0 + (size_t)j * n, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+    cgs2_normalize(C, x64, tmp, j, Qt64);
+    launch_cast<double, T>(C->st, n, x64, w.x);
+    long long mvp = 0;
+    S.dacg_its[j] = dacg<T>(C, w, j, QtT, o.tol_dacg, o.itmax_dacg, &mvp);
+    S.mvp_dacg += mvp;
+    launch_cast<T, double>(C->st, n, w.x, u);
+    C->sync();
+    S.t_dacg += now_s() - t0;
+
+    // ---- Newton phase
+    t0 = now_s();
+    cgs2_normalize(C, u, tmp, j, Qt64);
+    double *r_old = rA, *r_new = rB;
+    T *uT = fp64 ? (T *)u : w.u, *AuT = fp64 ? (T *)Au : w.Au, *rT = fp64 ? (T *)r_old : w.r;
+    outer_eval<T>(C, u, Au, r_old, fp64 ? nullptr : w.u, fp64 ? nullptr : w.Au, fp64 ? nullptr : w.r);
+    S.mvp_newton++;
+    DevCtl h = C->readctl();
+    double theta = h.otheta, rn = h.orn;
+    std::deque<int> ring;  // chronological slots
+    int k = 0;
+    while (rn > o.tol * theta && k < o.itmax) {
+      const int m = j + 1;
+      VList<T> Q = QtT;
+      Q.p[j] = uT;
+      VList<T> SL{}, RL{};
+      for (size_t t = 0; t < ring.size(); t++) {
+        SL.p[t] = w.S[ring[t]];
+        RL.p[t] = w.R[ring[t]];
+      }
+      const int kk = (int)ring.size();
+      PcgParams P;
+      P.theta = theta;
+      P.tol_pcg = o.tol_pcg;
+      P.itmax = o.itmax_pcg;
+      P.tau = o.tol;
+      P.exit_rule = o.exit_rule;
+      P.xi = o.exit_xi;
+      P.sgn = -1.0;
+      P.eigtest = 1;
+      int its = 0, why = 0;
+      rT = fp64 ? (T *)r_old : w.r;
+      pcg<T>(C, w, P, rT, m, Q, kk, SL, RL, uT, AuT, w.s, &its, &why);
+      S.pcg_its[j] += its;
+      S.mvp_newton += its;
+      if (why == 4) S.pcg_breakdowns++;
+      // ---- outer step: u <- (u + s)/||u + s||, re-orthogonalised against v_1..v_{j-1} (double)
+      const int nbi = gridn(n);
+      if (3 + j <= 8)
+        hipLaunchKernelGGL((k_outer_add<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, u, w.s, r_old, x64, j, Qt64,
+                           area(L, 4));
+      else
+        hipLaunchKernelGGL((k_outer_add<T, 3 + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, u, w.s, r_old, x64, j,
+                           Qt64, area(L, 4));
+      hipLaunchKernelGGL(c_outer_add, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbi, j);
+      hipLaunchKernelGGL(c_inv_sqrt, dim3(1), dim3(1), 0, C->st, c, &c->onrm2, &c->dinv);
+      comb<double>(C, u, x64, 1.0, &c->dinv, nullptr, nullptr, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                   nullptr, nullptr);
+      cgs2_normalize(C, u, tmp, j, Qt64);
+      outer_eval<T>(C, u, Au, r_new, fp64 ? nullptr : w.u, fp64 ? nullptr : w.Au, fp64 ? nullptr : w.r);
+      S.mvp_newton++;
+      h = C->readctl();
+      const double alpha = h.oalpha, sn2 = h.osn2;
+      // ---- store the pair (s_k, r_k) in the k_max window (Sec. 4.4)
+      const bool insert = o.kmax > 0 && alpha < -1e-12 * std::sqrt(sn2) * rn;
+      int shift = 0;
+      if (insert) {
+        int slot;
+        if ((int)ring.size() == o.kmax) {
+          slot = ring.front();
+          ring.pop_front();
+          shift = 1;
+        } else {
+          slot = (int)ring.size();
+          // the first free slot: slots are used 0..kmax-1 before any reuse
+          std::vector<bool> used(o.kmax, false);
+          for (int q : ring) used[q] = true;
+          for (int q = 0; q < o.kmax; q++)
+            if (!used[q]) {
+              slot = q;
+              break;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(w.S[slot], w.s, sizeof(T) * n, hipMemcpyDeviceToDevice, C->st));
+        launch_cast<double, T>(C->st, n, r_old, w.R[slot]);
+        ring.push_back(slot);
+      } else {
+        S.bfgs_skipped++;
+      }
+      // ---- Gram blocks (double): new row/column of M, Qt^T s_new, and u^T S for the new u
+      const int kn = (int)ring.size();
+      if (kn > 0) {
+        VList<T> X{}, Y{};
+        int D = 0;
+        if (insert) {
+          const T *snew = w.S[ring.back()], *rnew = w.R[ring.back()];
+          for (int t = 0; t < kn; t++) {
+            X.p[D] = snew;
+            Y.p[D++] = w.R[ring[t]];
+          }
+          for (int t = 0; t < kn - 1; t++) {
+            X.p[D] = w.S[ring[t]];
+            Y.p[D++] = rnew;
+          }
+          for (int q = 0; q < j; q++) {
+            X.p[D] = QtT.p[q];
+            Y.p[D++] = snew;
+          }
+        }
+        for (int t = 0; t < kn; t++) {
+          X.p[D] = uT;
+          Y.p[D++] = w.S[ring[t]];
+        }
+        int nb = launch_multidot<T, double>(L, n, D, X, Y, area(L, 6), nullptr);
+        hipLaunchKernelGGL(c_gram, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 6), nb, shift, insert ? 1 : 0, kn, j);
+      }
+      std::swap(r_old, r_new);
+      theta = h.otheta;
+      rn = h.orn;
+      k++;
+    }
+    S.outer_its[j] = k;
+    S.relres[j] = rn / theta;
+    S.converged[j] = rn <= o.tol * theta;
+    lam[j] = theta;
+    HIPCHK(hipMemcpyAsync(V64 + (size_t)j * n, u, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+    if (!fp64) launch_cast<double, T>(C->st, n, u, w.Qm + (size_t)j * n);
+    C->sync();
+    S.t_newton += now_s() - t0;
+  }
+  // ---- sort ascending, fix signs, write outputs
+  std::vector<int> idx(p);
+  for (int j = 0; j < p; j++) idx[j] = j;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+  if (C->evecs_last) C->release(C->evecs_last);
+  C->evecs_last = C->alloc<double>((size_t)n * p);
+  double *pm = area(L, 7), *pi = area(L, 7) + kNBMax;
+  for (int jj = 0; jj < p; jj++) {
+    const double *v = V64 + (size_t)idx[jj] * n;
+    const int nb = gridn(n);
+    hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(kBlock), 0, C->st, n, v, pm);
+    hipLaunchKernelGGL(k_firstbig, dim3(nb), dim3(kBlock), 0, C->st, n, v, pm, nb, pi);
+    hipLaunchKernelGGL(k_sign_copy, dim3(nb), dim3(kBlock), 0, C->st, n, v, pi, nb, C->evecs_last + (size_t)jj * n);
+  }
+  bnx_stats So = S;
+  for (int jj = 0; jj < p; jj++) {
+    evals[jj] = lam[idx[jj]];
+    So.dacg_its[jj] = S.dacg_its[idx[jj]];
+    So.outer_its[jj] = S.outer_its[idx[jj]];
+    So.pcg_its[jj] = S.pcg_its[idx[jj]];
+    So.relres[jj] = S.relres[idx[jj]];
+    So.converged[jj] = S.converged[idx[jj]];
+  }
+  if (evecs)
+    HIPCHK(hipMemcpyAsync(evecs, C->evecs_last, sizeof(double) * n * p,
+                          C->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, C->st));
+  C->sync();
+  C->evals_last.assign(evals, evals + p);
+  C->p_last = p;
+  C->prec_last = fp64 ? BNX_FP64 : BNX_MIXED;
+  C->solved = true;
+  bool allc = true;
+  for (int jj = 0; jj < p; jj++) allc = allc && So.converged[jj];
+  So.status = allc ? BNX_OK : BNX_NOT_CONVERGED;
+  So.levels_L = C->an.levL.nlev;
+  So.levels_Lt = C->an.levLt.nlev;
+  So.shift_used = C->shift_used;
+  So.t_factor = C->t_factor;
+  if (st) *st = So;
+  return (bnx_status)So.status;
+}
+
+// ------------------------------------------------------------------ backward
+// out = (I - QQ^T) x  (double, CGS twice), out != x
+void project_out(bnx_ctx *C, double *out, const double *x, int m, const VList<double> &Q, double *tmp) {
+  const Launch L = C->launch();
+  const int n = C->n;
+  DevCtl *c = C->ctl;
+  HIPCHK(hipMemcpyAsync(out, x, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+  VList<double> X{}, Y{};
+  for (int q = 0; q < m; q++) {
+    X.p[q] = Q.p[q];
+    Y.p[q] = out;
+  }
+  for (int pass = 0; pass < 2; pass++) {
+    const int nb = launch_multidot<double, double>(L, n, m, X, Y, area(L, 6), nullptr);
+    hipLaunchKernelGGL(c_outer_cgs, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 6), nb, m, 0);
+    comb<double>(C, tmp, out, 1.0, nullptr, nullptr, nullptr, m, Q, c->oz, -1.0, 0, VList<double>{}, nullptr, nullptr);
+    HIPCHK(hipMemcpyAsync(out, tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+  }
+}
+
+double norm2_host(bnx_ctx *C, const double *x) {
+  const Launch L = C->launch();
+  VList<double> X = vl<double>({x});
+  const int nb = launch_multidot<double, double>(L, C->n, 1, X, X, area(L, 6), nullptr);
+  hipLaunchKernelGGL(c_reduce_to, dim3(1), dim3(kBlock), 0, C->st, C->ctl->bz, area(L, 6), nb, 1);
+  return std::sqrt(C->readctl().bz[0]);
+}
+
+template <typename T>
+void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev, double *gv) {
+  const int n = C->n, p = C->p_last;
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const bool fp64 = std::is_same<T, double>::value;
+  const double *V = C->evecs_last;
+  Work<T> w;
+  make_work<T>(C, w, 0, p);
+  struct Guard {
+    bnx_ctx *C;
+    Work<T> *w;
+    std::vector<double *> extra;
+    ~Guard() {
+      free_work<T>(C, *w);
+      for (double *q : extra) C->release(q);
+    }
+  } guard{C, &w, {}};
+  auto dalloc = [&](size_t cnt) {
+    double *q = C->alloc<double>(cnt);
+    guard.extra.push_back(q);
+    return q;
+  };
+  double *ge = dalloc(p), *lam = dalloc(p), *xi = dalloc(n), *eta = dalloc(n), *res = dalloc(n), *tmp = dalloc(n);
+  double *Ae = dalloc(n), *rhs = dalloc(n), *tmp2 = dalloc(n), *scal = dalloc(4);
+  HIPCHK(hipMemcpyAsync(ge, g_evals, sizeof(double) * p, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(lam, C->evals_last.data(), sizeof(double) * p, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemsetAsync(&c->err, 0, sizeof(int), C->st));
+  launch_fill<double>(C->st, C->nnz, gv, 0.0);
+  // sum_i g_evals[i] v_i v_i^T on the pattern
+  hipLaunchKernelGGL(k_grad_lambda, dim3(gridn(n)), dim3(kBlock), 0, C->st, n, C->rp, C->ci, p, V, ge, gv);
+  if (!g_evecs_dev) {
+    C->sync();
+    return;
+  }
+  if (!fp64)
+    for (int q = 0; q < p; q++) launch_cast<double, T>(C->st, n, V + (size_t)q * n, w.Qm + (size_t)q * n);
+  Mat<double> A64 = C->mat<double>();
+  for (int i = 0; i < p; i++) {
+    const double *G = g_evecs_dev + (size_t)i * n;
+    if (!(norm2_host(C, G) > 0.0)) continue;
+    const int m = i + 1;
+    VList<double> Vl{};
+    for (int j = 0; j < m; j++) Vl.p[j] = V + (size_t)j * n;
+    // explicit part along v_j, j < i: xi = sum_j v_j (v_j^T G)/(lambda_j - lambda_i)
+    if (i > 0) {
+      VList<double> Gl{};
+      for (int j = 0; j < i; j++) Gl.p[j] = G;
+      const int nb = launch_multidot<double, double>(L, n, i, Vl, Gl, area(L, 6), nullptr);
+      hipLaunchKernelGGL(c_adj_coef, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 6), nb, i, lam, i);
+      comb<double>(C, xi, nullptr, 0.0, nullptr, nullptr, nullptr, i, Vl, c->bz, 1.0, 0, VList<double>{}, nullptr,
+                   nullptr);
+    } else {
+      launch_fill<double>(C->st, n, xi, 0.0);
+    }
+    // eta in the complement of Q = [v_1..v_i]: (I-QQ^T)(A - lambda_i I)(I-QQ^T) eta = (I-QQ^T) G
+    VList<T> Q{};
+    for (int q = 0; q < m; q++) Q.p[q] = fp64 ? (const T *)(V + (size_t)q * n) : w.Qm + (size_t)q * n;
+    project_out(C, rhs, G, m, Vl, tmp);
+    const double rhs_n = norm2_host(C, rhs);
+    launch_fill<double>(C->st, n, eta, 0.0);
+    HIPCHK(hipMemcpyAsync(res, rhs, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+    PcgParams P;
+    P.theta = C->evals_last[i];
+    P.itmax = C->adj_itmax;
+    P.tau = 0.0;
+    P.exit_rule = 0;
+    P.eigtest = 0;
+    P.sgn = 1.0;
+    if (fp64) {
+      P.tol_pcg = C->adj_tol;
+      int its = 0, why = 0;
+      pcg<T>(C, w, P, (const T *)res, m, Q, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, (T *)eta, &its, &why);
+    } else {
+      // float PCG inside double iterative refinement
+      P.tol_pcg = 1e-4;
+      double resn = rhs_n;
+      for (int round = 0; round < 40 && resn > C->adj_tol * rhs_n; round++) {
+        launch_cast<double, T>(C->st, n, res, w.r);
+        int its = 0, why = 0;
+        pcg<T>(C, w, P, w.r, m, Q, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, w.s, &its, &why);
+        launch_cast<T, double>(C->st, n, w.s, tmp);
+        // eta += delta  (coefficient 1 via scal[0])
+        hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal, 1.0);
+        comb<double>(C, tmp2, eta, 1.0, nullptr, tmp, scal, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                     nullptr, nullptr);
+        HIPCHK(hipMemcpyAsync(eta, tmp2, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+        // res = rhs - (I-QQ^T)(A eta - lambda eta)
+        launch_spmv<double>(L, A64, eta, Ae, 0, VList<double>{}, 0, VList<double>{}, nullptr, nullptr);
+        hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 1, -C->evals_last[i]);
+        comb<double>(C, tmp, Ae, 1.0, nullptr, eta, scal + 1, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                     nullptr, nullptr);
+        project_out(C, tmp2, tmp, m, Vl, Ae);
+        hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 2, -1.0);
+        comb<double>(C, res, rhs, 1.0, nullptr, tmp2, scal + 2, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                     nullptr, nullptr);
+        resn = norm2_host(C, res);
+      }
+    }
+    // xi += eta; g_vals -= 1/2 (xi v_i^T + v_i xi^T) on the pattern
+    hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 3, 1.0);
+    comb<double>(C, tmp, xi, 1.0, nullptr, eta, scal + 3, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{}, nullptr,
+                 nullptr);
+    hipLaunchKernelGGL(k_grad_vec, dim3(gridn(n)), dim3(kBlock), 0, C->st, n, C->rp, C->ci, V + (size_t)i * n, tmp, gv);
+  }
+  DevCtl h = C->readctl();
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+}
+
+// ------------------------------------------------------------------ factor
+void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
+  const double t0 = now_s();
+  Analysis &an = C->an;
+  const int n = C->n;
+  const int nnzL = an.nnzL;
+  if (!C->Lrp) {
+    C->Lrp = C->alloc<int>(n + 1);
+    C->Lci = C->alloc<int>(nnzL);
+    C->mapL = C->alloc<int>(nnzL);
+    C->Ltrp = C->alloc<int>(n + 1);
+    C->Ltci = C->alloc<int>(nnzL);
+    C->mapLt = C->alloc<int>(nnzL);
+    C->levL = C->alloc<int>(n);
+    C->levLt = C->alloc<int>(n);
+    C->Lv = C->alloc<double>(nnzL);
+    C->Ltv = C->alloc<double>(nnzL);
+    C->Lv32 = C->alloc<float>(nnzL);
+    C->Ltv32 = C->alloc<float>(nnzL);
+    HIPCHK(hipMemcpyAsync(C->Lrp, an.Lrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->Lci, an.Lci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->mapL, an.mapL.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->Ltrp, an.Ltrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->Ltci, an.Ltci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->mapLt, an.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->levL, an.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->levLt, an.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+  }
+  double a = 0.0;
+  for (;;) {
+    hipLaunchKernelGGL(k_ic0_gather, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapL, C->val, C->Lv);
+    HIPCHK(hipMemsetAsync(C->dflag, 0, sizeof(int), C->st));
+    for (int l = 0; l < an.levL.nlev; l++) {
+      const int r0 = an.levL.ptr[l], r1 = an.levL.ptr[l + 1];
+      hipLaunchKernelGGL(k_ic0_level, dim3((r1 - r0 + 127) / 128), dim3(128), 0, C->st, r0, r1, C->levL, C->Lrp,
+                         C->Lci, C->Lv, a, C->dflag);
+    }
+    HIPCHK(hipMemcpyAsync(C->hflag, C->dflag, sizeof(int), hipMemcpyDeviceToHost, C->st));
+    C->sync();
+    if (C->hflag[0] == 0) break;
+    a = (a == 0.0) ? shift0 : 2.0 * a;
+    if (shift0 <= 0.0 || a > shift_max) throw ApiError{BNX_E_NOT_SPD, "IC(0) breakdown beyond shift_max"};
+  }
+  C->shift_used = a;
+  hipLaunchKernelGGL(k_gather_d, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapLt, C->Lv, C->Ltv);
+  launch_cast<double, float>(C->st, nnzL, C->Lv, C->Lv32);
+  launch_cast<double, float>(C->st, nnzL, C->Ltv, C->Ltv32);
+  C->sync();
+  C->t_factor = now_s() - t0;
+  C->factored = true;
+  C->solved = false;
+}
+
+template <typename F>
+bnx_status guarded(bnx_ctx *C, F &&f) {
+  try {
+    C->err.clear();
+    return f();
+  } catch (const ApiError &e) {
+    C->err = e.msg;
+    return e.code;
+  } catch (const HipError &e) {
+    C->err = e.msg;
+    return BNX_E_HIP;
+  } catch (const std::bad_alloc &) {
+    C->err = "host allocation failed";
+    return BNX_E_NOMEM;
+  }
+}
+
+void upload_values(bnx_ctx *C, const double *val) {
+  HIPCHK(hipMemcpyAsync(C->val, val, sizeof(double) * C->nnz,
+                        C->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, C->st));
+  launch_cast<double, float>(C->st, C->nnz, C->val, C->val32);
+  // diagonal must be positive
+  std::vector<double> hv(C->nnz);
+  HIPCHK(hipMemcpyAsync(hv.data(), C->val, sizeof(double) * C->nnz, hipMemcpyDeviceToHost, C->st));
+  C->sync();
+  for (int i = 0; i < C->n; i++)
+    for (int e = C->an.rp[i]; e < C->an.rp[i + 1]; e++)
+      if (C->an.ci[e] == i && !(hv[e] > 0.0)) throw ApiError{BNX_E_NOT_SPD, "non-positive diagonal entry"};
+  C->factored = false;
+  C->solved = false;
+}
+
+bool prec_ok(int p) { return p == BNX_FP64 || p == BNX_MIXED; }
+
+}  // namespace
+
+// ================================================================== C-ABI
+namespace {
+template <typename T>
+static void ic_apply_t(bnx_ctx *C, int which, const T *b, T *x, T *tmp) {
+  const Launch L = C->launch();
+  HIPCHK(hipMemsetAsync(&C->ctl->err, 0, sizeof(int), C->st));
+  if (which == 0) launch_trsv<T>(L, C->tri<T>(true), b, x, 0, VList<T>{}, nullptr, nullptr);
+  else if (which == 1) launch_trsv<T>(L, C->tri<T>(false), b, x, 0, VList<T>{}, nullptr, nullptr);
+  else {
+    launch_trsv<T>(L, C->tri<T>(true), b, tmp, 0, VList<T>{}, nullptr, nullptr);
+    launch_trsv<T>(L, C->tri<T>(false), tmp, x, 0, VList<T>{}, nullptr, nullptr);
+  }
+  if (C->readctl().err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+}
+
+template <typename T>
+static void prec_apply_t(bnx_ctx *C, int k, const double *S, const double *R, int m, const double *Q, const double *g,
+                         double *out) {
+  const int n = C->n;
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const bool fp64 = std::is_same<T, double>::value;
+  Work<T> w;
+  make_work<T>(C, w, k, m);
+  std::vector<T *> extra;
+  VList<T> SL{}, RL{}, QL{};
+  for (int s = 0; s < k; s++) {
+    launch_cast<double, T>(C->st, n, S + (size_t)s * n, w.S[s]);
+    launch_cast<double, T>(C->st, n, R + (size_t)s * n, w.R[s]);
+    SL.p[s] = w.S[s];
+    RL.p[s] = w.R[s];
+  }
+  for (int q = 0; q < m; q++) {
+    launch_cast<double, T>(C->st, n, Q + (size_t)q * n, w.Qm + (size_t)q * n);
+    QL.p[q] = w.Qm + (size_t)q * n;
+  }
+  launch_cast<double, T>(C->st, n, g, w.g);
+  HIPCHK(hipMemsetAsync(&c->err, 0, sizeof(int), C->st));
+  gram_full<T>(C, k, SL, RL, m, QL);
+  VList<T> X{}, Y{};
+  for (int s = 0; s < k; s++) {
+    X.p[s] = SL.p[s];
+    Y.p[s] = w.g;
+  }
+  for (int q = 0; q < m; q++) {
+    X.p[k + q] = QL.p[q];
+    Y.p[k + q] = w.g;
+  }
+  int nb = launch_multidot<T, T>(L, n, k + m, X, Y, area(L, 3), nullptr);
+  if (k + m == 0) nb = 1;
+  hipLaunchKernelGGL(c_prec_a, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nb, k, m);
+  launch_trsv<T>(L, C->tri<T>(true), w.g, w.z, k, RL, c->a, nullptr);
+  launch_trsv<T>(L, C->tri<T>(false), w.z, w.c0, 0, RL, nullptr, nullptr);
+  VList<T> mX{}, mY{};
+  for (int s = 0; s < k; s++) {
+    mX.p[s] = RL.p[s];
+    mY.p[s] = w.c0;
+  }
+  for (int q = 0; q < m; q++) {
+    mX.p[k + q] = QL.p[q];
+    mY.p[k + q] = w.c0;
+  }
+  mX.p[k + m] = w.g;
+  mY.p[k + m] = w.c0;
+  nb = launch_multidot<T, T>(L, n, k + m + 1, mX, mY, area(L, 3), nullptr);
+  hipLaunchKernelGGL(c_pcg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nb);
+  hipLaunchKernelGGL((k_pcg_newp<T>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, c, w.c0, k, SL, m, QL, w.p, 0);
+  launch_cast<T, double>(C->st, n, w.p, out);
+  DevCtl h = C->readctl();
+  free_work<T>(C, w);
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  (void)fp64;
+}
+
+template <typename T>
+static void corr_solve_t(bnx_ctx *C, int m, const double *Q, int k, const double *S, const double *R, double tol_pcg,
+                         int itmax_pcg, double tau, int exit_rule, double xi, double *s, int *its, int *reason) {
+  const int n = C->n;
+  Work<T> w;
+  make_work<T>(C, w, k, m);
+  double *u = C->alloc<double>(n), *Au = C->alloc<double>(n), *r = C->alloc<double>(n);
+  HIPCHK(hipMemcpyAsync(u, Q + (size_t)(m - 1) * n, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+  HIPCHK(hipMemsetAsync(&C->ctl->err, 0, sizeof(int), C->st));
+  outer_eval<T>(C, u, Au, r, w.u, w.Au, w.r);
+  const double theta = C->readctl().otheta;
+  VList<T> SL{}, RL{}, QL{};
+  for (int t = 0; t < k; t++) {
+    launch_cast<double, T>(C->st, n, S + (size_t)t * n, w.S[t]);
+    launch_cast<double, T>(C->st, n, R + (size_t)t * n, w.R[t]);
+    SL.p[t] = w.S[t];
+    RL.p[t] = w.R[t];
+  }
+  for (int q = 0; q < m; q++) {
+    launch_cast<double, T>(C->st, n, Q + (size_t)q * n, w.Qm + (size_t)q * n);
+    QL.p[q] = w.Qm + (size_t)q * n;
+  }
+  gram_full<T>(C, k, SL, RL, m, QL);
+  PcgParams P;
+  P.theta = theta;
+  P.tol_pcg = tol_pcg;
+  P.itmax = itmax_pcg;
+  P.tau = tau;
+  P.exit_rule = exit_rule;
+  P.xi = xi;
+  P.sgn = -1.0;
+  P.eigtest = 1;
+  pcg<T>(C, w, P, w.r, m, QL, k, SL, RL, w.u, w.Au, w.s, its, reason);
+  launch_cast<T, double>(C->st, n, w.s, s);
+  C->sync();
+  C->release(u);
+  C->release(Au);
+  C->release(r);
+  free_work<T>(C, w);
+}
+
+template <typename T>
+static void dacg_t(bnx_ctx *C, int m, const double *Qt, const double *x0, double tol, int itmax, double *x, int *its) {
+  const int n = C->n;
+  Work<T> w;
+  make_work<T>(C, w, 0, m);
+  double *x64 = C->alloc<double>(n), *tmp = C->alloc<double>(n);
+  VList<double> Q64{};
+  VList<T> QT{};
+  for (int q = 0; q < m; q++) {
+    Q64.p[q] = Qt + (size_t)q * n;
+    launch_cast<double, T>(C->st, n, Qt + (size_t)q * n, w.Qm + (size_t)q * n);
+    QT.p[q] = w.Qm + (size_t)q * n;
+  }
+  HIPCHK(hipMemcpyAsync(x64, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+  HIPCHK(hipMemsetAsync(&C->ctl->err, 0, sizeof(int), C->st));
+  cgs2_normalize(C, x64, tmp, m, Q64);
+  launch_cast<double, T>(C->st, n, x64, w.x);
+  long long mvp = 0;
+  *its = dacg<T>(C, w, m, QT, tol, itmax, &mvp);
+  launch_cast<T, double>(C->st, n, w.x, x);
+  C->sync();
+  C->release(x64);
+  C->release(tmp);
+  free_work<T>(C, w);
+}
+
+}  // namespace
+
+extern "C" {
+
+void bnx_default_solve_opts(bnx_solve_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->p = 10;
+  o->tol = 1e-8;
+  o->itmax = 100;
+  o->tol_dacg = 1e-2;
+  o->itmax_dacg = 5000;
+  o->tol_pcg = 1e-2;
+  o->itmax_pcg = 20;
+  o->kmax = 5;
+  o->precision = BNX_FP64;
+  o->exit_rule = 1;
+  o->exit_xi = 0.1;
+  o->seed = 0;
+  o->x0 = nullptr;
+  o->keep_bfgs = 0;
+}
+
+void bnx_default_factor_opts(bnx_factor_opts *o) {
+  if (!o) return;
+  o->shift0 = 1e-3;
+  o->shift_max = 1.0;
+}
+
+bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
+                          const double *val, int device_ptrs, void *hip_stream) {
+  if (!out) return BNX_E_ARG;
+  *out = nullptr;
+  if (n < 1 || nnz < n || n > INT32_MAX || nnz > INT32_MAX || !rowptr || !col || !val) return BNX_E_ARG;
+  bnx_ctx *C = new (std::nothrow) bnx_ctx;
+  if (!C) return BNX_E_NOMEM;
+  C->n = (int)n;
+  C->nnz = (int)nnz;
+  C->device_ptrs = device_ptrs ? 1 : 0;
+  C->st = (hipStream_t)hip_stream;
+  bnx_status s = guarded(C, [&]() -> bnx_status {
+    C->an.n = C->n;
+    C->an.nnz = C->nnz;
+    C->an.rp.resize(n + 1);
+    C->an.ci.resize(nnz);
+    if (device_ptrs) {
+      HIPCHK(hipMemcpy(C->an.rp.data(), rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(C->an.ci.data(), col, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+    } else {
+      std::memcpy(C->an.rp.data(), rowptr, sizeof(int) * (n + 1));
+      std::memcpy(C->an.ci.data(), col, sizeof(int) * nnz);
+    }
+    std::string v = validate_csr(C->n, C->nnz, C->an.rp.data(), C->an.ci.data());
+    if (!v.empty()) throw ApiError{BNX_E_ARG, v};
+    analyse(C->an);
+    C->group = spmv_group((double)nnz / (double)n);
+    C->rp = C->alloc<int>(n + 1);
+    C->ci = C->alloc<int>(nnz);
+    C->val = C->alloc<double>(nnz);
+    C->val32 = C->alloc<float>(nnz);
+    C->ctl = C->alloc<DevCtl>(1);
+    C->part = C->alloc<double>((size_t)8 * kPartSlots * kNBMax);
+    C->counter = C->alloc<int>(4);
+    C->dflag = C->alloc<int>(4);
+    HIPCHK(hipHostMalloc((void **)&C->hctl, sizeof(DevCtl), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&C->hflag, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipMemsetAsync(C->ctl, 0, sizeof(DevCtl), C->st));
+    HIPCHK(hipMemcpyAsync(C->rp, C->an.rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
+    HIPCHK(hipMemcpyAsync(C->ci, C->an.ci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, C->st));
+    upload_values(C, val);
+    return BNX_OK;
+  });
+  if (s != BNX_OK) {
+    fprintf(stderr, "bnx_create_csr: %s\n", C->err.c_str());
+    delete C;
+    return s;
+  }
+  *out = C;
+  return BNX_OK;
+}
+
+bnx_status bnx_set_values(bnx_ctx *C, const double *val) {
+  if (!C || !val) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    upload_values(C, val);
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_factor(bnx_ctx *C, const bnx_factor_opts *opts) {
+  if (!C) return BNX_E_ARG;
+  bnx_factor_opts o;
+  bnx_default_factor_opts(&o);
+  if (opts) o = *opts;
+  return guarded(C, [&]() -> bnx_status {
+    factor_impl(C, o.shift0, o.shift_max);
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_solve(bnx_ctx *C, const bnx_solve_opts *opts, double *evals, double *evecs, bnx_stats *stats) {
+  if (!C || !opts || !evals) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    const bnx_solve_opts &o = *opts;
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_solve"};
+    if (o.p < 1 || o.p > BNX_MAX_P || o.p > C->n) throw ApiError{BNX_E_ARG, "p out of range"};
+    if (o.kmax < 0 || o.kmax > BNX_MAX_KMAX) throw ApiError{BNX_E_ARG, "kmax out of range"};
+    if (!prec_ok(o.precision)) throw ApiError{BNX_E_ARG, "unknown precision"};
+    if (o.itmax < 0 || o.itmax_pcg < 1 || o.itmax_dacg < 0 || !(o.tol > 0)) throw ApiError{BNX_E_ARG, "bad iteration parameters"};
+    if (o.precision == BNX_FP64) return solve_impl<double>(C, o, evals, evecs, stats);
+    return solve_impl<float>(C, o, evals, evecs, stats);
+  });
+}
+
+bnx_status bnx_set_adjoint_params(bnx_ctx *C, double tol_adj, int itmax_adj) {
+  if (!C || !(tol_adj > 0) || itmax_adj < 1) return BNX_E_ARG;
+  C->adj_tol = tol_adj;
+  C->adj_itmax = itmax_adj;
+  return BNX_OK;
+}
+
+bnx_status bnx_backward(bnx_ctx *C, const double *g_evals, const double *g_evecs, double *g_vals) {
+  if (!C || !g_evals || !g_vals) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->solved) throw ApiError{BNX_E_STATE, "bnx_backward needs a preceding bnx_solve"};
+    const int n = C->n, p = C->p_last;
+    double *gv = g_vals, *GV = (double *)g_evecs;
+    std::vector<double *> tmp;
+    if (!C->device_ptrs) {
+      gv = C->alloc<double>(C->nnz);
+      tmp.push_back(gv);
+      if (g_evecs) {
+        GV = C->alloc<double>((size_t)n * p);
+        tmp.push_back(GV);
+        HIPCHK(hipMemcpyAsync(GV, g_evecs, sizeof(double) * n * p, hipMemcpyHostToDevice, C->st));
+      }
+    }
+    struct G {
+      bnx_ctx *C;
+      std::vector<double *> &t;
+      ~G() {
+        for (double *q : t) C->release(q);
+      }
+    } g{C, tmp};
+    if (C->prec_last == BNX_FP64) backward_impl<double>(C, g_evals, GV, gv);
+    else backward_impl<float>(C, g_evals, GV, gv);
+    if (!C->device_ptrs) {
+      HIPCHK(hipMemcpyAsync(g_vals, gv, sizeof(double) * C->nnz, hipMemcpyDeviceToHost, C->st));
+      C->sync();
+    }
+    return BNX_OK;
+  });
+}
+
+const char *bnx_last_error(const bnx_ctx *C) { return C ? C->err.c_str() : "null context"; }
+
+void bnx_destroy(bnx_ctx *C) {
+  if (!C) return;
+  (void)hipStreamSynchronize(C->st);
+  delete C;
+}
+
+bnx_status bnx_set_profiling(bnx_ctx *C, int on) {
+  if (!C) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    C->sync();
+    C->prof.reset();
+    C->prof.on = on != 0;
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_kernel_time(bnx_ctx *C, int kernel, double *ms_total, long long *launches) {
+  if (!C || kernel < 0 || kernel >= Profiler::kIds || !ms_total || !launches) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    C->sync();
+    C->prof.drain();
+    *ms_total = C->prof.ms[kernel];
+    *launches = C->prof.count[kernel];
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_set_trsv_mode(bnx_ctx *C, int mode) {
+  if (!C || (mode != 0 && mode != 1)) return BNX_E_ARG;
+  C->trsv_mode = mode;
+  return BNX_OK;
+}
+
+// ------------------------------------------------------------------ step-level entry points
+bnx_status bnx_spmv(bnx_ctx *C, int precision, const double *x, double *y) {
+  if (!C || !x || !y || !prec_ok(precision)) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    const Launch L = C->launch();
+    if (precision == BNX_FP64) {
+      launch_spmv<double>(L, C->mat<double>(), x, y, 0, VList<double>{}, 0, VList<double>{}, nullptr, nullptr);
+    } else {
+      float *xf = C->alloc<float>(C->n), *yf = C->alloc<float>(C->n);
+      launch_cast<double, float>(C->st, C->n, x, xf);
+      launch_spmv<float>(L, C->mat<float>(), xf, yf, 0, VList<float>{}, 0, VList<float>{}, nullptr, nullptr);
+      launch_cast<float, double>(C->st, C->n, yf, y);
+      C->sync();
+      C->release(xf);
+      C->release(yf);
+    }
+    C->sync();
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_ic_apply(bnx_ctx *C, int precision, int which, const double *b, double *x) {
+  if (!C || !b || !x || !prec_ok(precision) || which < 0 || which > 2) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_ic_apply"};
+    const int n = C->n;
+    if (precision == BNX_FP64) {
+      double *tmp = C->alloc<double>(n);
+      ic_apply_t<double>(C, which, b, x, tmp);
+      C->release(tmp);
+    } else {
+      float *bf = C->alloc<float>(n), *xf = C->alloc<float>(n), *tf = C->alloc<float>(n);
+      launch_cast<double, float>(C->st, n, b, bf);
+      ic_apply_t<float>(C, which, bf, xf, tf);
+      launch_cast<float, double>(C->st, n, xf, x);
+      C->sync();
+      C->release(bf);
+      C->release(xf);
+      C->release(tf);
+    }
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_prec_apply(bnx_ctx *C, int precision, int k, const double *S, const double *R, int m, const double *Q,
+                          const double *g, double *c) {
+  if (!C || !g || !c || !prec_ok(precision) || k < 0 || k > BNX_MAX_KMAX || m < 0 || m > BNX_MAX_P + 1)
+    return BNX_E_ARG;
+  if ((k > 0 && (!S || !R)) || (m > 0 && !Q)) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_prec_apply"};
+    if (precision == BNX_FP64) prec_apply_t<double>(C, k, S, R, m, Q, g, c);
+    else prec_apply_t<float>(C, k, S, R, m, Q, g, c);
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_correction_solve(bnx_ctx *C, int precision, int m, const double *Q, int k, const double *S,
+                                const double *R, double tol_pcg, int itmax_pcg, double tau, int exit_rule,
+                                double exit_xi, double *s, int *its, int *reason) {
+  if (!C || !Q || !s || !its || !reason || !prec_ok(precision) || m < 1 || m > BNX_MAX_P + 1 || k < 0 ||
+      k > BNX_MAX_KMAX || itmax_pcg < 1)
+    return BNX_E_ARG;
+  if (k > 0 && (!S || !R)) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_correction_solve"};
+    if (precision == BNX_FP64) corr_solve_t<double>(C, m, Q, k, S, R, tol_pcg, itmax_pcg, tau, exit_rule, exit_xi, s, its, reason);
+    else corr_solve_t<float>(C, m, Q, k, S, R, tol_pcg, itmax_pcg, tau, exit_rule, exit_xi, s, its, reason);
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_dacg(bnx_ctx *C, int precision, int m, const double *Qt, const double *x0, double tol, int itmax,
+                    double *x, int *its) {
+  if (!C || !x0 || !x || !its || !prec_ok(precision) || m < 0 || m > BNX_MAX_P || itmax < 0 || (m > 0 && !Qt))
+    return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_dacg"};
+    if (precision == BNX_FP64) dacg_t<double>(C, m, Qt, x0, tol, itmax, x, its);
+    else dacg_t<float>(C, m, Qt, x0, tol, itmax, x, its);
+    return BNX_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,352 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle, step by step.
+
+Inputs are seeded synthetic matrices from ``workloads``; every expected value
+comes from ``oracle`` or from closed forms / dense library routines.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1312_1553_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1312_1553_amd import bnx  # noqa: E402
+
+FP64, MIXED = bnx.FP64, bnx.MIXED
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+_CACHE = {}
+
+
+def mats():
+    if "m" not in _CACHE:
+        _CACHE["m"] = {
+            "laplace2d_32": W.laplacian_2d(32),
+            "diffusion_12": W.diffusion_3d(12, seed=1),
+            "elasticity_3": W.elasticity_q1(3, seed=2),
+            "rgg_3000": W.rgg_laplacian(3000, seed=3),
+        }
+    return _CACHE["m"]
+
+
+def solver_for(A):
+    s = bnx.Solver(A.rowptr, A.col, A.val)
+    return s
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle.build()
+    return oracle
+
+
+# ----------------------------------------------------------------------------- a1: SpMV
+@pytest.mark.parametrize("name", ["laplace2d_32", "diffusion_12", "elasticity_3", "rgg_3000"])
+def test_spmv(oracle_mod, name):
+    A = mats()[name]
+    say("case spmv", name, A.n, A.nnz)
+    S = solver_for(A)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(A.n)
+    ref = oracle_mod.spmv(A, x)
+    scale = abs(A.to_scipy()) @ np.abs(x)
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    bnx.bnx_spmv(S.h, FP64, dev(x), y)
+    assert np.all(np.abs(host(y) - ref) <= 4e-16 * 16 * scale + 1e-300)
+    bnx.bnx_spmv(S.h, MIXED, dev(x), y)
+    assert np.all(np.abs(host(y) - ref) <= 1e-6 * scale)
+    S.close()
+
+
+# ----------------------------------------------------------------------------- a0, a5, a6: IC(0) and the solves
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["laplace2d_32", "diffusion_12", "elasticity_3", "rgg_3000"])
+def test_ic_solves(oracle_mod, name, mode):
+    A = mats()[name]
+    say("case ic", name, "mode", mode)
+    S = solver_for(A)
+    bnx.bnx_set_trsv_mode(S.h, mode)
+    S.factor()
+    F = oracle_mod.ic0(A)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    refs = [oracle_mod.lsolve(F, b), oracle_mod.ltsolve(F, b), oracle_mod.ltsolve(F, oracle_mod.lsolve(F, b))]
+    for which in range(3):
+        bnx.bnx_ic_apply(S.h, FP64, which, dev(b), x)
+        got = host(x)
+        err = np.abs(got - refs[which]).max() / np.abs(refs[which]).max()
+        assert err < 1e-12, (which, err)
+        bnx.bnx_ic_apply(S.h, MIXED, which, dev(b), x)
+        err = np.abs(host(x) - refs[which]).max() / np.abs(refs[which]).max()
+        assert err < 1e-4, (which, err)
+    S.close()
+
+
+def test_ic_shift_on_breakdown(oracle_mod):
+    import json, os
+    import scipy.sparse as sp
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "kershaw.json")))
+    A = W._from_scipy(sp.csr_matrix(np.array(g["A"], float)))
+    S = solver_for(A)
+    S.factor(1e-3, 1.0)
+    F = oracle_mod.ic0(A, 1e-3, 1.0)
+    b = np.array([1.0, -2.0, 0.5, 3.0])
+    x = torch.empty(4, dtype=torch.float64, device="cuda")
+    bnx.bnx_ic_apply(S.h, FP64, 2, dev(b), x)
+    np.testing.assert_allclose(host(x), oracle_mod.ltsolve(F, oracle_mod.lsolve(F, b)), rtol=1e-13)
+    with pytest.raises(bnx.BnxError) as ei:
+        S.factor(0.0, 0.0)
+    assert ei.value.code == -2
+    S.close()
+
+
+# ----------------------------------------------------------------------------- a4-a8: Alg. 1
+@pytest.mark.parametrize("k,m", [(0, 0), (0, 3), (1, 2), (5, 4)])
+def test_prec_apply(oracle_mod, k, m):
+    A = mats()["diffusion_12"]
+    say("case prec", k, m)
+    Ad = A.to_scipy()
+    S = solver_for(A)
+    S.factor()
+    F = oracle_mod.ic0(A)
+    rng = np.random.default_rng(3 + k + m)
+    Sv = rng.standard_normal((k, A.n))
+    Rv = -(Ad @ Sv.T).T + 0.05 * rng.standard_normal((k, A.n)) if k else np.zeros((0, A.n))
+    Q = np.linalg.qr(rng.standard_normal((A.n, max(m, 1))))[0].T[:m]
+    g = rng.standard_normal(A.n)
+    if m:
+        g -= Q.T @ (Q @ g)
+    ref = oracle_mod.bfgspk(F, Sv if k else None, Rv if k else None, Q if m else None, g)
+    c = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    bnx.bnx_prec_apply(S.h, FP64, k, dev(Sv) if k else None, dev(Rv) if k else None, m, dev(Q) if m else None,
+                       dev(g), c)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+    bnx.bnx_prec_apply(S.h, MIXED, k, dev(Sv) if k else None, dev(Rv) if k else None, m, dev(Q) if m else None,
+                       dev(g), c)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    assert err < 1e-4, err
+    S.close()
+
+
+# ----------------------------------------------------------------------------- a1-a9: one PCG solve
+def _near(Ad, j, eps, seed):
+    w, V = np.linalg.eigh(Ad)
+    rng = np.random.default_rng(seed)
+    u = V[:, j] + eps * rng.standard_normal(len(w))
+    u -= V[:, :j] @ (V[:, :j].T @ u)
+    return u / np.linalg.norm(u), V
+
+
+@pytest.mark.parametrize("j,k", [(0, 0), (2, 3)])
+def test_correction_solve(oracle_mod, j, k):
+    A = mats()["diffusion_12"]
+    say("case pcg", j, k)
+    Ad = A.to_scipy().toarray()
+    S = solver_for(A)
+    S.factor()
+    F = oracle_mod.ic0(A)
+    u, V = _near(Ad, j, 2e-3, 10 + j)
+    Q = np.vstack([V[:, :j].T, u])
+    theta = u @ Ad @ u
+    Au = Ad @ u
+    r = Au - theta * u
+    rng = np.random.default_rng(20)
+    Sv = rng.standard_normal((k, A.n)) * 1e-3
+    Rv = -(Ad @ Sv.T).T + 1e-5 * rng.standard_normal((k, A.n)) if k else np.zeros((0, A.n))
+    for exit_rule, tol, itmax in ((0, 1e-10, 60), (1, 1e-2, 20)):
+        s_ref, its_ref, why_ref = oracle_mod.pcg(A, F, theta, Q, u, Au, r, Sv if k else None, Rv if k else None,
+                                                 tol_pcg=tol, itmax_pcg=itmax, tau=1e-8, exit_rule=exit_rule)
+        s = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        its, why = bnx.bnx_correction_solve(S.h, FP64, Q.shape[0], dev(Q), k, dev(Sv) if k else None,
+                                            dev(Rv) if k else None, tol, itmax, 1e-8, exit_rule, 0.1, s)
+        say("  rule", exit_rule, "its", its, its_ref, "why", why, why_ref)
+        assert (its, why) == (its_ref, why_ref)
+        err = np.abs(host(s) - s_ref).max() / np.abs(s_ref).max()
+        assert err < 1e-9, err
+        its32, why32 = bnx.bnx_correction_solve(S.h, MIXED, Q.shape[0], dev(Q), k, dev(Sv) if k else None,
+                                                dev(Rv) if k else None, tol, itmax, 1e-8, exit_rule, 0.1, s)
+        if exit_rule == 1:
+            err = np.abs(host(s) - s_ref).max() / np.abs(s_ref).max()
+            assert err < 1e-3, err
+    S.close()
+
+
+# ----------------------------------------------------------------------------- a11: DACG
+def test_dacg(oracle_mod):
+    A = mats()["diffusion_12"]
+    say("case dacg")
+    Ad = A.to_scipy().toarray()
+    S = solver_for(A)
+    S.factor()
+    F = oracle_mod.ic0(A)
+    w, V = np.linalg.eigh(Ad)
+    Qt = V[:, :2].T.copy()
+    x0 = W.initial_block(A.n, 1, 5)[0]
+    for tol in (1e-2, 1e-6):
+        xr, its_r, hist = oracle_mod.dacg(A, F, Qt, x0, tol=tol, itmax=2000)
+        x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        its = bnx.bnx_dacg(S.h, FP64, 2, dev(Qt), dev(x0), tol, 2000, x)
+        say("  tol", tol, "its", its, its_r)
+        assert abs(its - its_r) <= 1
+        xg = host(x)
+        q = xg @ Ad @ xg
+        assert abs(np.linalg.norm(xg) - 1) < 1e-12
+        assert np.linalg.norm(Ad @ xg - q * xg) <= tol * q * 1.0001
+        assert abs(Qt @ xg).max() < 1e-10
+        if its == its_r:
+            assert np.abs(xg - xr).max() < 1e-8
+        its32 = bnx.bnx_dacg(S.h, MIXED, 2, dev(Qt), dev(x0), 1e-2, 2000, x)
+        xg = host(x)
+        assert np.linalg.norm(Ad @ xg - (xg @ Ad @ xg) * xg) <= 1.05e-2 * (xg @ Ad @ xg)
+    S.close()
+
+
+# ----------------------------------------------------------------------------- Alg. 2 end to end
+def check_pairs(A, ev, V, tol):
+    M = A.to_scipy()
+    for j in range(len(ev)):
+        assert np.linalg.norm(M @ V[j] - ev[j] * V[j]) <= tol * ev[j] * (1 + 1e-6)
+    assert np.abs(V @ V.T - np.eye(len(ev))).max() < 1e-10
+
+
+def test_solve_laplace2d_closed_form(oracle_mod):
+    A, p = W.config_small()
+    x0 = W.initial_block(A.n, p, 0)
+    S = solver_for(A)
+    S.factor()
+    ref = W.laplacian_2d_eigs(32)[:p]
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0)
+    for prec in (FP64, MIXED):
+        say("case solve laplace2d", prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        ev = ev.numpy()
+        V = host(V)
+        say("  stats", st)
+        np.testing.assert_allclose(ev, ref, rtol=1e-10)
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, V, 1e-8)
+        assert st["status"] == 0
+        if prec == FP64:
+            assert st["dacg_its"] == st_o["dacg_its"]
+            assert abs(sum(st["pcg_its"]) - sum(st_o["pcg_its"])) <= 0.1 * sum(st_o["pcg_its"])
+    S.close()
+
+
+@pytest.mark.parametrize("name,p", [("diffusion_12", 6), ("elasticity_3", 5), ("rgg_3000", 3)])
+def test_solve_matches_oracle(oracle_mod, name, p):
+    A = mats()[name]
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case solve", name, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        ev = ev.numpy()
+        V = host(V)
+        say("  stats", st, "oracle", st_o)
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, V, 1e-8)
+    S.close()
+
+
+def test_solve_bad_calls():
+    A = mats()["laplace2d_32"]
+    S = solver_for(A)
+    with pytest.raises(bnx.BnxError) as ei:  # solve before factor
+        o = bnx.bnx_default_solve_opts()
+        o.p = 2
+        bnx.bnx_solve(S.h, o, np.empty(2), torch.empty((2, A.n), dtype=torch.float64, device="cuda"))
+    assert ei.value.code == -6
+    S.factor()
+    with pytest.raises(bnx.BnxError):
+        S.solve(64)
+    S.close()
+    bad = W.laplacian_2d(4)
+    val = bad.val.copy()
+    val[0] = -1.0
+    with pytest.raises(bnx.BnxError):
+        bnx.Solver(bad.rowptr, bad.col, val)
+    col = bad.col.copy()
+    col[1], col[2] = col[2], col[1]
+    with pytest.raises(bnx.BnxError):
+        bnx.Solver(bad.rowptr, col, bad.val)
+
+
+def test_not_converged_status():
+    A = mats()["diffusion_12"]
+    S = solver_for(A)
+    S.factor()
+    ev, V, st = S.solve(2, itmax=1, tol_dacg=0.5)
+    assert st["status"] == 1
+
+
+# ----------------------------------------------------------------------------- a13: backward
+def test_backward_matches_oracle_and_dense(oracle_mod):
+    N, p = 8, 4
+    pat, logk, w = W.diffusion_grad_case(N, seed=4)
+    A = pat.csr(logk)
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, _, _ = oracle_mod.solve(A, p, x0=x0, tol=1e-12)
+    GVo = np.zeros((p, A.n))
+    GVo[0] = 2 * w * V_o[0]
+    g_o = oracle_mod.backward(A, ev_o, V_o, np.ones(p), GVo, tol=1e-13)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case backward", prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, tol=1e-12)
+        Vh = host(V)
+        GV = np.zeros((p, A.n))
+        GV[0] = 2 * w * Vh[0]
+        g = host(S.backward(np.ones(p), dev(GV)))
+        err = np.abs(g - g_o).max() / np.abs(g_o).max()
+        say("  rel err vs oracle", err)
+        assert err < 1e-7
+
+
+def test_autograd_chain_matches_torch_eigh():
+    N, p = 6, 3
+    pat, logk, w = W.diffusion_grad_case(N, seed=4)
+    A = pat.csr(logk)
+    # dense reference (CPU, fp64)
+    lk = torch.tensor(logk, requires_grad=True)
+    vals = pat.values_torch(lk)
+    rows = torch.as_tensor(np.repeat(np.arange(A.n), np.diff(A.rowptr)))
+    M = torch.zeros(A.n, A.n, dtype=torch.float64).index_put((rows, torch.as_tensor(A.col).long()), vals)
+    lam, V = torch.linalg.eigh(M)
+    (lam[:p].sum() + (torch.tensor(w) * V[:, 0] ** 2).sum()).backward()
+    ref = lk.grad.numpy()
+    # HIP path through autograd
+    S = solver_for(A)
+    EigSolve = bnx.eigsh_autograd()
+    lkg = torch.tensor(logk, requires_grad=True, device="cuda")
+    valsg = pat.values_torch(lkg)
+    ev, Vg = EigSolve.apply(valsg, S, p, FP64, {"tol": 1e-12, "x0": W.initial_block(A.n, p, 0)})
+    loss = ev.sum() + (torch.tensor(w, device="cuda") * Vg[0] ** 2).sum()
+    loss.backward()
+    got = host(lkg.grad)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9)
