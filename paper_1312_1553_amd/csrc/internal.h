@@ -89,6 +89,7 @@ struct Tri {
   const int *lev_rows = nullptr;
   std::vector<int> lev_ptr;  // host copy for level launches
   int nlev = 0;
+  int max_rows = 0;          // largest level
   bool lower = true;         // true: diag last (L); false: diag first (L^T)
 };
 

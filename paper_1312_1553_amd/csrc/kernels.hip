@@ -324,8 +324,13 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
     if (prof) L.prof->end(L.st, pid, ev);
     return;
   }
+  // In-flight window: about three levels' worth of 64-row chunks.  Waves beyond
+  // that would only poll, and their polling traffic slows the dependency chain.
   const int nchunks = (F.n + 63) / 64;
-  int waves = L.sf_waves < nchunks ? L.sf_waves : nchunks;
+  int waves = L.sf_waves > 0 ? L.sf_waves : 3 * ((F.max_rows + 63) / 64);
+  if (waves < 16) waves = 16;
+  if (waves > 2048) waves = 2048;
+  if (waves > nchunks) waves = nchunks;
   int nb = (waves + 3) / 4;
   hipLaunchKernelGGL((k_sentinel<T>), dim3(grid_for(F.n, 1024)), dim3(kBlock), 0, L.st, (size_t)F.n, x, L.counter,
                      gate);

@@ -784,7 +784,7 @@ struct bnx_ctx {
   int *hflag = nullptr;    // pinned
   bool factored = false, solved = false;
   double shift_used = 0.0, t_factor = 0.0;
-  int trsv_mode = 0, sf_waves = 2048;
+  int trsv_mode = 0, sf_waves = 0;  // 0: window from the level sizes
   double adj_tol = 1e-12;
   int adj_itmax = 2000;
   // last solve
@@ -875,6 +875,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   const Levels &lv = lower ? an.levL : an.levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
+  F.max_rows = lv.max_rows;
   return F;
 }
 template <>
@@ -889,6 +890,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
   const Levels &lv = lower ? an.levL : an.levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
+  F.max_rows = lv.max_rows;
   return F;
 }
 
@@ -1846,6 +1848,7 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     if (!v.empty()) throw ApiError{BNX_E_ARG, v};
     analyse(C->an);
     C->group = spmv_group((double)nnz / (double)n);
+    if (const char *e = getenv("BNX_SF_WAVES")) C->sf_waves = atoi(e);  // tuning override of the solve window
     C->rp = C->alloc<int>(n + 1);
     C->ci = C->alloc<int>(nnz);
     C->val = C->alloc<double>(nnz);
