@@ -84,6 +84,8 @@ def main():
             S.factor()
             ev, V, st = S.solve(p, precision=prec, x0=x0d)
             stats.append(st)
+            print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
+                  flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kt = {kname: bnx.bnx_kernel_time(S.h, kid) for kname, kid in bnx.KERNEL_IDS.items()}

@@ -94,6 +94,7 @@ typedef struct {
     int levels_L, levels_Lt;    /* dependency levels of the IC(0) triangular solves */
     double shift_used;          /* IC(0) diagonal shift actually used */
     double t_factor, t_dacg, t_newton;  /* seconds */
+    int dacg_restarts;          /* returns from a stalled Newton phase to DACG (see bnx_solve) */
 } bnx_stats;
 
 void bnx_default_solve_opts(bnx_solve_opts *o);
@@ -134,6 +135,11 @@ bnx_status bnx_factor(bnx_ctx *ctx, const bnx_factor_opts *opts);
  *         v_{j+1}, unit norm, with its first entry of magnitude above
  *         1e-12 ||v||_inf positive.
  *  stats: may be NULL.
+ * When the Newton phase of a pair stalls (a PCG solve takes no step, or the
+ * outer residual fails to drop below 0.9x in two consecutive steps) the start
+ * was not close enough for Newton (Sec. 4.1): DACG is resumed from the current
+ * iterate to 0.1 ||r||/theta (kept within [tol, tol_dacg]), the BFGS history is
+ * restarted and Newton continues; at most 5 such returns per pair.
  * Returns BNX_OK, or BNX_NOT_CONVERGED with results still written.
  * Errors: BNX_E_STATE (no factor), BNX_E_ARG, BNX_E_BREAKDOWN, BNX_E_HIP.
  * The eigenpairs are kept in the context for bnx_backward.
@@ -211,9 +217,14 @@ bnx_status bnx_correction_solve(bnx_ctx *ctx, int precision, int m, const double
 bnx_status bnx_dacg(bnx_ctx *ctx, int precision, int m, const double *Qt, const double *x0, double tol,
                     int itmax, double *x, int *its);
 
-/* Triangular-solve schedule: 0 = one persistent sync-free kernel per solve
- * (rows in level order, per-row completion carried by the solution value),
- * 1 = one kernel launch per dependency level.  Default 0. */
+/* Triangular-solve schedule of the IC(0) solves:
+ *  0 = LDS-staged blocks (default): one workgroup per block of consecutive rows
+ *      in solve order, the block's solution held in LDS, rows sorted by level
+ *      inside the block, dependencies on earlier blocks read from global memory;
+ *  1 = one kernel launch per dependency level;
+ *  2 = one persistent sync-free kernel over all rows in level order, each row's
+ *      completion carried by its solution value in global memory.
+ * All three compute the same substitution.  Errors: BNX_E_ARG. */
 bnx_status bnx_set_trsv_mode(bnx_ctx *ctx, int mode);
 
 /* Live timing of the hot kernels with HIP events recorded on the context's

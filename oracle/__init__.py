@@ -39,7 +39,7 @@ class Stats(C.Structure):
                 ("converged", C.c_int * MAXP), ("relres", C.c_double * MAXP), ("mvp_dacg", C.c_longlong),
                 ("mvp_newton", C.c_longlong), ("bfgs_skipped", C.c_int), ("pcg_breakdowns", C.c_int),
                 ("ntrace", C.c_int), ("status", C.c_int), ("shift_used", C.c_double), ("t_factor", C.c_double),
-                ("t_dacg", C.c_double), ("t_newton", C.c_double)]
+                ("t_dacg", C.c_double), ("t_newton", C.c_double), ("dacg_restarts", C.c_int)]
 
     def as_dict(self, p: int) -> dict:
         return {
@@ -48,7 +48,7 @@ class Stats(C.Structure):
             "relres": list(self.relres[:p]), "mvp_dacg": self.mvp_dacg, "mvp_newton": self.mvp_newton,
             "bfgs_skipped": self.bfgs_skipped, "pcg_breakdowns": self.pcg_breakdowns,
             "status": self.status, "shift_used": self.shift_used, "t_factor": self.t_factor,
-            "t_dacg": self.t_dacg, "t_newton": self.t_newton,
+            "t_dacg": self.t_dacg, "t_newton": self.t_newton, "dacg_restarts": self.dacg_restarts,
         }
 
 

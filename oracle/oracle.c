@@ -33,7 +33,12 @@
  *   restarted on A + a*diag(A), a = shift0, 2*shift0, ... <= shift_max;
  *   DACG is a preconditioned Fletcher-Reeves nonlinear CG on the Rayleigh
  *   quotient over the complement of the converged eigenvectors, with an exact
- *   line search (closed-form minimiser of q(x + a d)).
+ *   line search (closed-form minimiser of q(x + a d));
+ *   when the Newton phase stalls (a PCG solve takes no step, or the outer
+ *   residual fails to drop below 0.9x in two consecutive steps) the start was
+ *   not close enough in the sense of Sec. 4.1: DACG is resumed from the current
+ *   iterate to 0.1 ||r||/theta (within [tol, tol_DACG]), the BFGS history is
+ *   restarted, and Newton continues (at most 5 times per eigenpair).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -53,6 +58,7 @@ typedef struct {
     long long mvp_dacg, mvp_newton;
     int bfgs_skipped, pcg_breakdowns, ntrace, status;
     double shift_used, t_factor, t_dacg, t_newton;
+    int dacg_restarts;
 } or_stats;
 
 static double now_s(void) {
@@ -441,7 +447,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
         double theta = dot(n, u, Au);
         for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
         double rn = nrm2(n, r);
-        int k = 0;
+        int k = 0, slow = 0, restarts = 0;
         while (rn > o->tol * theta && k < o->itmax) {
             int its = 0;
             int why = or_pcg(&P, theta, j + 1, Qm, u, Au, r, W.k, W.S, W.R, W.alpha, o->tol_pcg, o->itmax_pcg,
@@ -470,9 +476,33 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
                 double *T = trace + 8 * (size_t)st->ntrace++;
                 T[0] = j; T[1] = k; T[2] = theta; T[3] = rn; T[4] = alpha; T[5] = sn2; T[6] = theta1; T[7] = its;
             }
+            /* stall: no PCG step, or the residual fails to drop below 0.9x twice in a row */
+            slow = (its == 0 || rn1 > 0.9 * rn) ? slow + 1 : 0;
             theta = theta1;
             rn = rn1;
             k++;
+            if ((its == 0 || slow >= 2) && restarts < 5 && rn > o->tol * theta && k < o->itmax) {
+                /* return to DACG from the current iterate with a tighter tolerance, restart the BFGS history */
+                double t2 = 0.1 * rn / theta;
+                if (t2 > o->tol_dacg) t2 = o->tol_dacg;
+                if (t2 < o->tol) t2 = o->tol;
+                double td2 = now_s();
+                st->dacg_its[j] += or_dacg(&P, j, Qm, u, t2, o->itmax_dacg, xn, NULL, 0, &st->mvp_dacg, work);
+                st->t_dacg += now_s() - td2;
+                copy(n, xn, u);
+                cgs(n, j, Qm, u, z);
+                cgs(n, j, Qm, u, z);
+                scal(n, 1.0 / nrm2(n, u), u);
+                W.k = 0;
+                or_spmv(n, rp, ci, v, u, Au);
+                st->mvp_newton++;
+                theta = dot(n, u, Au);
+                for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
+                rn = nrm2(n, r);
+                restarts++;
+                st->dacg_restarts++;
+                slow = 0;
+            }
         }
         st->outer_its[j] = k;
         st->relres[j] = rn / theta;

@@ -42,7 +42,8 @@ class Stats(C.Structure):
                 ("converged", C.c_int * MAX_P), ("relres", C.c_double * MAX_P), ("mvp_dacg", C.c_longlong),
                 ("mvp_newton", C.c_longlong), ("bfgs_skipped", C.c_int), ("pcg_breakdowns", C.c_int),
                 ("status", C.c_int), ("levels_L", C.c_int), ("levels_Lt", C.c_int), ("shift_used", C.c_double),
-                ("t_factor", C.c_double), ("t_dacg", C.c_double), ("t_newton", C.c_double)]
+                ("t_factor", C.c_double), ("t_dacg", C.c_double), ("t_newton", C.c_double),
+                ("dacg_restarts", C.c_int)]
 
     def as_dict(self, p):
         return {"dacg_its": list(self.dacg_its[:p]), "outer_its": list(self.outer_its[:p]),
@@ -50,7 +51,8 @@ class Stats(C.Structure):
                 "relres": list(self.relres[:p]), "mvp_dacg": self.mvp_dacg, "mvp_newton": self.mvp_newton,
                 "bfgs_skipped": self.bfgs_skipped, "pcg_breakdowns": self.pcg_breakdowns, "status": self.status,
                 "levels_L": self.levels_L, "levels_Lt": self.levels_Lt, "shift_used": self.shift_used,
-                "t_factor": self.t_factor, "t_dacg": self.t_dacg, "t_newton": self.t_newton}
+                "t_factor": self.t_factor, "t_dacg": self.t_dacg, "t_newton": self.t_newton,
+                "dacg_restarts": self.dacg_restarts}
 
 
 EXPORTS = ["bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_create_csr", "bnx_set_values", "bnx_factor",

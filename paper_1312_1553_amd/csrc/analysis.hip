@@ -55,6 +55,7 @@ std::string validate_csr(int n, int nnz, const int *rp, const int *ci) {
 }
 
 static void build_levels(int n, const std::vector<int> &lev, Levels &L) {
+  L.level = lev;
   int nlev = 0;
   for (int i = 0; i < n; i++) nlev = std::max(nlev, lev[i] + 1);
   L.nlev = nlev;
@@ -119,6 +120,80 @@ void analyse(Analysis &an) {
     lev[i] = l;
   }
   build_levels(n, lev, an.levLt);
+}
+
+void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs) {
+  const int n = an.n;
+  const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
+  const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
+  bs.n = n;
+  bs.B = B;
+  bs.nblocks = (n + B - 1) / B;
+  auto pos_of = [&](int i) { return lower ? i : n - 1 - i; };
+  auto row_at = [&](int p) { return lower ? p : n - 1 - p; };
+  // sort key: level of the row in the whole dependency graph
+  const std::vector<int> &glev = lower ? an.levL.level : an.levLt.level;
+  std::vector<int> llev(n, 0);
+  bs.max_local_levels = 0;
+  for (int p = 0; p < n; p++) {
+    llev[p] = glev[row_at(p)];
+  }
+  for (int b = 0; b < bs.nblocks; b++) {
+    int lo = INT32_MAX, hi = -1;
+    for (int p = b * B; p < std::min(n, b * B + B); p++) {
+      lo = std::min(lo, llev[p]);
+      hi = std::max(hi, llev[p]);
+    }
+    bs.max_local_levels = std::max(bs.max_local_levels, hi - lo + 1);
+  }
+  // sort each block by (level, position)
+  bs.perm.assign(n, 0);
+  bs.slot.assign(n, 0);
+  bs.diagmap.assign(n, 0);
+  std::vector<int> order;
+  for (int b = 0; b < bs.nblocks; b++) {
+    const int p0 = b * B, p1 = std::min(n, p0 + B);
+    order.resize(p1 - p0);
+    for (int p = p0; p < p1; p++) order[p - p0] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return llev[a] < llev[c]; });
+    for (int k = p0; k < p1; k++) {
+      const int p = order[k - p0];
+      const int i = row_at(p);
+      bs.perm[k] = i;
+      bs.slot[k] = p - p0;
+      bs.diagmap[k] = lower ? rp[i + 1] - 1 : rp[i];
+    }
+  }
+  // ELL slices of 64 sorted rows
+  bs.nslices = (n + 63) / 64;
+  bs.slice_ptr.assign(bs.nslices + 1, 0);
+  bs.slice_nnz.assign(bs.nslices, 0);
+  for (int sl = 0; sl < bs.nslices; sl++) {
+    int mx = 0;
+    for (int k = sl * 64; k < std::min(n, sl * 64 + 64); k++) {
+      const int i = bs.perm[k];
+      mx = std::max(mx, rp[i + 1] - rp[i] - 1);
+    }
+    bs.slice_nnz[sl] = mx;
+    bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * mx;
+  }
+  bs.ell = bs.slice_ptr[bs.nslices];
+  bs.ref.assign(bs.ell, INT32_MIN);
+  bs.valmap.assign(bs.ell, -1);
+  for (int k = 0; k < n; k++) {
+    const int sl = k / 64, lane = k % 64;
+    const int i = bs.perm[k];
+    const int b0 = (k / B) * B;  // block start (sorted index == position range start)
+    const int e0 = lower ? rp[i] : rp[i] + 1, e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
+    int e = 0;
+    for (int q = e0; q < e1; q++, e++) {
+      const int j = ci[q];
+      const int pj = pos_of(j);
+      const int at = bs.slice_ptr[sl] + 64 * e + lane;
+      bs.ref[at] = (pj >= b0) ? -(pj - b0) - 1 : j;
+      bs.valmap[at] = q;
+    }
+  }
 }
 
 }  // namespace bnx

@@ -14,6 +14,7 @@ constexpr int kMaxQ = kMaxP + 1;
 constexpr int kMaxVec = 80;    // vectors in one kernel argument list
 constexpr int kNBMax = 2048;   // blocks of a streaming kernel (partials per dot)
 constexpr int kPartSlots = 80; // dots per partial area
+constexpr int kAreas = 10;     // partial areas
 constexpr int kBlock = 256;
 
 // Pointer list passed by value to kernels.
@@ -51,9 +52,31 @@ struct Buf {
 // Level schedule of a triangular factor.
 struct Levels {
   int nlev = 0;
+  std::vector<int> level;  // n: level of each row
   std::vector<int> ptr;   // nlev+1
   std::vector<int> rows;  // n, rows sorted by level
   int max_rows = 0;
+};
+
+// Block schedule of one triangular solve ("LDS-staged" sync-free solve).
+// Rows are taken in solve order (position pos = i for L, n-1-i for L^T, so every
+// dependency has a smaller position), cut into blocks of B consecutive
+// positions, and each block is sorted by the rows' level in the whole
+// dependency graph, so that all blocks advance through the levels together and
+// the rows a block needs from earlier blocks are produced early.  Sorted index k = block start + rank in block.
+// Row data is stored as 64-row ELL slices: entry e of lane l of slice s is at
+// slice_ptr[s] + 64 e + l; ref >= 0 is an external dependency (global row id),
+// ref < 0 an in-block one (LDS slot -ref-1); padding has ref = INT_MIN.
+struct BlockSched {
+  int n = 0, B = 0, nblocks = 0, nslices = 0, ell = 0;
+  int max_local_levels = 0;
+  std::vector<int> perm;       // n: original row of sorted index k
+  std::vector<int> slot;       // n: LDS slot (position - block start) of sorted index k
+  std::vector<int> diagmap;    // n: factor value index of the diagonal of row perm[k]
+  std::vector<int> slice_ptr;  // nslices+1
+  std::vector<int> slice_nnz;  // nslices
+  std::vector<int> ref;        // ell entries
+  std::vector<int> valmap;     // ell entries: factor value index, -1 for padding
 };
 
 // Host-side analysis of the CSR pattern (done once per context).
@@ -69,9 +92,13 @@ struct Analysis {
 std::string validate_csr(int n, int nnz, const int *rp, const int *ci);
 // Build L / L^T patterns and level schedules.
 void analyse(Analysis &an);
+// Block schedule of the forward (lower = true: rows of L, diag last) or backward
+// (rows of L^T, diag first) solve with B rows per block.
+void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs);
 
 // ----------------------------------------------------------------- launchers
 int spmv_group(double mean_nnz);
+int block_rows_for(int elem_bytes);
 
 template <typename T>
 struct Mat {
@@ -79,10 +106,24 @@ struct Mat {
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;
   int group = 8;
+  // SELL-64 copy (used when present): slice s holds rows 64s..64s+63, entry e of
+  // lane l at ell_ptr[s] + 64 e + l; padding has column = row and value 0.
+  const int *ell_ptr = nullptr, *ell_len = nullptr, *ell_col = nullptr;
+  const T *ell_val = nullptr;
+};
+
+// Device copy of a BlockSched with values of precision T.
+template <typename T>
+struct DevBlk {
+  int n = 0, B = 0, nblocks = 0;
+  const int *perm = nullptr, *slot = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
+  const T *diag = nullptr, *val = nullptr;
 };
 
 template <typename T>
 struct Tri {
+  DevBlk<T> blk;
+  void *blk_scratch = nullptr;  // n values: right-hand side in solve order
   int n = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;

@@ -5,6 +5,7 @@
 // Dot products are reduced deterministically: every block writes one partial
 // per dot, and a single-block control kernel sums the partials in fixed order.
 #include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -111,9 +112,69 @@ static int spmv_dispatch_d(const Launch &L, const Mat<T> &A, const T *x, T *y, i
 }
 
 // Number of blocks a SpMV launch uses (the control kernels need it).
+// SELL-64 SpMV: one row per lane, column-major entries inside each 64-row
+// slice, so value, column and (for banded matrices) x loads and the y store
+// are coalesced.  Same epilogue dots as k_spmv, computed by every lane.
+template <typename T, int MAXD>
+__global__ __launch_bounds__(kBlock) void k_spmv_ell(int n, const int *__restrict__ eptr, const int *__restrict__ elen,
+                                                     const int *__restrict__ ecol, const T *__restrict__ eval,
+                                                     const T *__restrict__ x, T *__restrict__ y, int ndy, VList<T> ly,
+                                                     int ndx, VList<T> lx, double *part, const int *gate) {
+  if (gate && *gate) return;
+  constexpr int NA = MAXD > 0 ? MAXD : 1;
+  T acc[NA];
+#pragma unroll
+  for (int d = 0; d < NA; d++) acc[d] = T(0);
+  for (int row = blockIdx.x * kBlock + threadIdx.x; row < n; row += gridDim.x * kBlock) {
+    const int sl = row >> 6, lane = row & 63;
+    const int base = eptr[sl] + lane, len = elen[sl];
+    T s = T(0);
+    // batches of 8 entries: all column and value loads issued before the x gathers
+    for (int e0 = 0; e0 < len; e0 += 8) {
+      int cc[8];
+      T vv[8];
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const bool ok = e0 + q < len;
+        cc[q] = ok ? ecol[base + 64 * (e0 + q)] : row;
+        vv[q] = ok ? eval[base + 64 * (e0 + q)] : T(0);
+      }
+      T xx[8];
+#pragma unroll
+      for (int q = 0; q < 8; q++) xx[q] = x[cc[q]];
+#pragma unroll
+      for (int q = 0; q < 8; q++) s += vv[q] * xx[q];
+    }
+    y[row] = s;
+    if (MAXD > 0) {
+      const T xr = x[row];
+#pragma unroll
+      for (int d = 0; d < NA; d++) {
+        if (d < ndy) acc[d] += s * ly.p[d][row];
+        else if (d < ndy + ndx) acc[d] += xr * lx.p[d - ndy][row];
+      }
+    }
+  }
+  if (MAXD > 0) block_partials<T, NA>(acc, ndy + ndx, part);
+}
+
 template <typename T>
 static int spmv_switch(const Launch &L, const Mat<T> &A, const T *x, T *y, int ndy, const VList<T> &ly, int ndx,
                        const VList<T> &lx, double *part, const int *gate) {
+  if (A.ell_ptr) {
+    const int nd = ndy + ndx;
+    const int nb = grid_for((size_t)A.n, kNBMax);
+    if (nd == 0)
+      hipLaunchKernelGGL((k_spmv_ell<T, 0>), dim3(nb), dim3(kBlock), 0, L.st, A.n, A.ell_ptr, A.ell_len, A.ell_col,
+                         A.ell_val, x, y, 0, ly, 0, lx, part, gate);
+    else if (nd <= 6)
+      hipLaunchKernelGGL((k_spmv_ell<T, 6>), dim3(nb), dim3(kBlock), 0, L.st, A.n, A.ell_ptr, A.ell_len, A.ell_col,
+                         A.ell_val, x, y, ndy, ly, ndx, lx, part, gate);
+    else
+      hipLaunchKernelGGL((k_spmv_ell<T, 72>), dim3(nb), dim3(kBlock), 0, L.st, A.n, A.ell_ptr, A.ell_len, A.ell_col,
+                         A.ell_val, x, y, ndy, ly, ndx, lx, part, gate);
+    return nb;
+  }
   switch (A.group) {
     case 1: return spmv_dispatch_d<T, 1>(L, A, x, y, ndy, ly, ndx, lx, part, gate);
     case 2: return spmv_dispatch_d<T, 2>(L, A, x, y, ndy, ly, ndx, lx, part, gate);
@@ -303,13 +364,229 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
   }
 }
 
+// LDS-staged sync-free solve: one 1024-thread workgroup per block of B rows
+// (taken in block order from a ticket counter).  The block's solution lives in
+// LDS; in-block dependencies are read from LDS, external ones (earlier blocks)
+// from the global solution, both polled until they leave the sentinel state.
+// Each wave walks its 64-row slices of the block in order (rows sorted by local
+// level), so a lane only waits on rows of lower rank, which finish first.
+// Right-hand side in solve order and sentinel fill:  bp[k] = b[perm[k]] - sum_t coef[t] R_t[perm[k]],
+// x[i] = sentinel, counter = 0.  Makes every per-row load of the solve a rank-indexed (coalesced) load.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trsv_prep(int n, const int *__restrict__ perm, const T *__restrict__ b,
+                                                      int kfuse, VList<T> R, const double *coef, T *bp, T *x,
+                                                      int *counter, const int *gate) {
+  if (gate && *gate) return;
+  using U = typename Sentinel<T>::U;
+  U *xu = reinterpret_cast<U *>(x);
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
+    bp[k] = rhs_value(perm[k], b, kfuse, R, coef);
+    xu[k] = Sentinel<T>::bits;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
+}
+
+template <typename T, int NR>
+struct RowPre {
+  int row, my, sp, nz;
+  T d, s;
+  int rr[NR];
+  T vv[NR];
+};
+
+template <typename T, int NR>
+__device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int base, int k1, int lane,
+                                          RowPre<T, NR> &R) {
+  const int k = base + lane;
+  const int sl = base >> 6;
+  R.nz = F.slice_nnz[sl];
+  R.sp = F.slice_ptr[sl] + lane;
+  const bool ok = k < k1;
+  R.row = ok ? F.perm[k] : 0;
+  R.my = ok ? F.slot[k] : 0;
+  R.d = ok ? F.diag[k] : T(1);
+  R.s = ok ? bp[k] : T(0);
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    const bool has = ok && q < R.nz;
+    R.rr[q] = has ? F.ref[R.sp + 64 * q] : INT32_MIN;
+    R.vv[q] = has ? F.val[R.sp + 64 * q] : T(0);
+  }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, int *counter,
+                                                    int *err, const int *gate) {
+  if (gate && *gate) return;
+  using U = typename Sentinel<T>::U;
+  constexpr int NR = 4;  // dependencies cached in registers per row
+  __shared__ U xs[B];
+  __shared__ int blk_s;
+  if (threadIdx.x == 0) blk_s = atomicAdd(counter, 1);
+  for (int i = threadIdx.x; i < B; i += 1024) xs[i] = Sentinel<T>::bits;
+  __syncthreads();
+  const int blk = blk_s;
+  if (blk >= F.nblocks) return;
+  U *xu = reinterpret_cast<U *>(x);
+  const int n = F.n;
+  const int k0 = blk * B, k1 = (k0 + B < n) ? k0 + B : n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int base = k0 + wave * 64;
+  RowPre<T, NR> cur, nxt;
+  if (base < k1) row_fetch<T, NR>(F, bp, base, k1, lane, nxt);
+  for (; base < k1; base += 1024) {
+    cur = nxt;
+    // prefetch the next round while this one waits for its dependencies
+    if (base + 1024 < k1) row_fetch<T, NR>(F, bp, base + 1024, k1, lane, nxt);
+    bool fin = base + lane >= k1;
+    int nown = 0;
+#pragma unroll
+    for (int q = 0; q < NR; q++)
+      if (cur.rr[q] != INT32_MIN) nown = q + 1;
+    const int nlong = (!fin && cur.nz > NR) ? cur.nz : NR;  // entries beyond the register cache
+    // masks of cached dependencies: in-block (LDS) and external (global)
+    unsigned need_l = 0, need_g = 0;
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      if (q < nown) {
+        if (cur.rr[q] < 0) need_l |= 1u << q;
+        else need_g |= 1u << q;
+      }
+    }
+    T xv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; q++) xv[q] = T(0);
+    unsigned seen = 0;
+    bool cached_done = false;
+    T s = cur.s;
+    int e = NR, spins = 0;
+    while (!fin) {
+      // 1) global polls for external dependencies: issued now, examined after the LDS phase
+      U gv[NR];
+#pragma unroll
+      for (int q = 0; q < NR; q++)
+        gv[q] = ((need_g & ~seen) >> q & 1u)
+                    ? __hip_atomic_load(&xu[cur.rr[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : Sentinel<T>::bits;
+      // 2) LDS phase: spin on in-block dependencies; a row whose dependencies are all in finishes here
+      for (int it = 0; it < 64 && !fin && (need_l & ~seen); it++, spins++) {
+#pragma unroll
+        for (int q = 0; q < NR; q++) {
+          if ((need_l & ~seen) >> q & 1u) {
+            const U u = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (u != Sentinel<T>::bits) {
+              xv[q] = from_bits<T>(u);
+              seen |= 1u << q;
+            }
+          }
+        }
+        if (seen == (need_l | need_g) && nlong == NR) {
+#pragma unroll
+          for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
+          const U v = to_bits<T>(s / cur.d);
+          __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          fin = true;
+        }
+      }
+      if (fin) break;
+      // 3) results of the global polls
+#pragma unroll
+      for (int q = 0; q < NR; q++)
+        if (((need_g & ~seen) >> q & 1u) && gv[q] != Sentinel<T>::bits) {
+          xv[q] = from_bits<T>(gv[q]);
+          seen |= 1u << q;
+        }
+      if (seen == (need_l | need_g)) {
+        if (!cached_done) {
+#pragma unroll
+          for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
+          cached_done = true;
+        }
+        // rows longer than the register cache: the rest in order
+        bool blocked = false;
+        while (e < nlong) {
+          const int r = F.ref[cur.sp + 64 * e];
+          if (r == INT32_MIN) {
+            e = nlong;
+            break;
+          }
+          const U u = r < 0 ? __hip_atomic_load(&xs[-r - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                            : __hip_atomic_load(&xu[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (u == Sentinel<T>::bits) {
+            blocked = true;
+            break;
+          }
+          s -= F.val[cur.sp + 64 * e] * from_bits<T>(u);
+          e++;
+        }
+        if (!blocked) {
+          const U v = to_bits<T>(s / cur.d);
+          __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          fin = true;
+          break;
+        }
+      }
+      if (++spins > kSpinLimit) {
+        const U v = to_bits<T>(T(__builtin_nan("")));
+        __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr(err, 1);
+        fin = true;
+      } else if (!(need_l & ~seen)) {
+        __builtin_amdgcn_s_sleep(1);  // only global dependencies left
+      }
+    }
+  }
+}
+
+template <typename T>
+constexpr int blk_rows() {
+  return (128 * 1024) / (int)sizeof(T);
+}
+// Rows per block: the largest block whose solution fits 128 KiB of LDS, unless
+// overridden (BNX_BLK_ROWS, a power of two from 1024 up to that size).
+int block_rows_for(int elem_bytes) {
+  const int mx = elem_bytes == 8 ? blk_rows<double>() : blk_rows<float>();
+  if (const char *e = getenv("BNX_BLK_ROWS")) {
+    const int v = atoi(e);
+    if (v >= 1024 && v <= mx && (v & (v - 1)) == 0) return v;
+  }
+  return mx;
+}
+
+template <typename T, int B>
+static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
+  hipLaunchKernelGGL((k_trsv_blk<T, B>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, L.counter,
+                     &L.ctl->err, gate);
+}
+
 template <typename T>
 void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, const VList<T> &R,
                  const double *coef, const int *gate) {
+  if (L.trsv_mode == 0 && F.blk.nblocks > 0) {
+    const bool prof0 = L.prof && L.prof->on;
+    hipEvent_t ev0 = nullptr;
+    T *bp = reinterpret_cast<T *>(F.blk_scratch);
+    hipLaunchKernelGGL((k_trsv_prep<T>), dim3(grid_for(F.n, kNBMax)), dim3(kBlock), 0, L.st, F.n, F.blk.perm, b, kfuse,
+                       R, coef, bp, x, L.counter, gate);
+    if (prof0) L.prof->begin(L.st, &ev0);
+    switch (F.blk.B) {
+      case 1024: launch_blk<T, 1024>(L, F, bp, x, gate); break;
+      case 2048: launch_blk<T, 2048>(L, F, bp, x, gate); break;
+      case 4096: launch_blk<T, 4096>(L, F, bp, x, gate); break;
+      case 8192: launch_blk<T, 8192>(L, F, bp, x, gate); break;
+      case 16384: launch_blk<T, 16384>(L, F, bp, x, gate); break;
+      default: launch_blk<T, blk_rows<T>()>(L, F, bp, x, gate); break;
+    }
+    if (prof0) L.prof->end(L.st, (F.lower ? 2 : 4) + (sizeof(T) == 8 ? 0 : 1), ev0);
+    return;
+  }
   const bool prof = L.prof && L.prof->on;
   const int pid = (F.lower ? 2 : 4) + (sizeof(T) == 8 ? 0 : 1);
   hipEvent_t ev = nullptr;
-  if (L.trsv_mode == 1) {
+  if (L.trsv_mode == 1) {  // one launch per dependency level
     if (prof) L.prof->begin(L.st, &ev);
     for (int l = 0; l < F.nlev; l++) {
       int r0 = F.lev_ptr[l], r1 = F.lev_ptr[l + 1];

@@ -173,18 +173,30 @@ __global__ __launch_bounds__(kBlock) void k_pcg_eigres(int n, const DevCtl *c, c
 }
 
 // p = c0 - sum_s e_s S_s - sum_q zQ_q Q_q + beta p    (beta = 0 on the first application)
-template <typename T>
+// dots (when nd > 0): Q_q^T p (m), then (A Q_q)^T p (m): with them Q^T (A - theta I) p = (AQ)^T p - theta Q^T p
+template <typename T, int MAXD>
 __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, const T *c0, int k, VList<T> S, int m,
-                                                     VList<T> Q, T *p, int with_beta) {
+                                                     VList<T> Q, T *p, int with_beta, int nd, VList<T> AQ,
+                                                     double *part) {
   if (c->done) return;
   const T beta = (T)c->beta;
+  constexpr int NA = MAXD > 0 ? MAXD : 1;
+  T acc[NA];
+#pragma unroll
+  for (int d = 0; d < NA; d++) acc[d] = T(0);
   GRIDLOOP(i, n) {
     T v = c0[i];
     for (int s = 0; s < k; s++) v -= (T)c->e[s] * S.p[s][i];
     for (int q = 0; q < m; q++) v -= (T)c->zQ[q] * Q.p[q][i];
     if (with_beta) v += beta * p[i];
     p[i] = v;
+#pragma unroll
+    for (int d = 0; d < NA; d++) {
+      if (d < m && d < nd) acc[d] += Q.p[d][i] * v;
+      else if (d < nd) acc[d] += AQ.p[d - m][i] * v;
+    }
   }
+  if (MAXD > 0) bpart<T, NA>(acc, nd, part);
 }
 
 // ============================================================== PCG control kernels
@@ -260,19 +272,21 @@ __global__ void c_pcg_beta(DevCtl *c, const double *part, int nb) {
   c->rho = rho1;
 }
 
-// after SpMV: p^T ap, Q^T ap (m), p^T p, Q^T p (m)  ->  zy, p^T J p, gamma
-__global__ void c_pcg_gamma(DevCtl *c, const double *part, int nb) {
+// after SpMV (p^T ap, p^T p) and k_pcg_newp (Q^T p, (AQ)^T p)  ->  zy = Q^T (A - theta I) p, p^T J p, gamma
+__global__ void c_pcg_gamma(DevCtl *c, const double *part_s, int nbs, const double *part_p, int nbp) {
   if (c->done) return;
-  __shared__ double red[2 * kMaxQ + 2];
+  __shared__ double red[2];
+  __shared__ double rq[2 * kMaxQ];
   const int m = c->m;
-  reduce_parts(part, nb, 2 * (m + 1), red);
+  reduce_parts(part_s, nbs, 2, red);
+  reduce_parts(part_p, nbp, 2 * m, rq);
   if (threadIdx.x) return;
   const double th = c->theta;
-  const double pap = red[0], pp = red[m + 1];
+  const double pap = red[0], pp = red[1];
   double pJp = pap - th * pp;
   for (int q = 0; q < m; q++) {
-    const double qp = red[m + 2 + q];
-    c->zy[q] = red[1 + q] - th * qp;
+    const double qp = rq[q];
+    c->zy[q] = rq[m + q] - th * qp;
     c->Qp[q] = qp;
     pJp -= qp * c->zy[q];
   }
@@ -569,15 +583,17 @@ __global__ void c_dacg_qg(DevCtl *c, const double *part, int nb, int nq) {
   if (threadIdx.x < nq) c->Qg[threadIdx.x] = red[threadIdx.x];
 }
 
-// after SpMV Ad = A d with dots [d^T Ad, x^T Ad] (y-list) and [d^T Ax, d^T x, d^T d] (x-list)
-__global__ void c_dacg_alpha(DevCtl *c, const double *part, int nb) {
+// after the d update (dots d^T Ax, d^T x, d^T d) and SpMV Ad = A d (dot d^T Ad)
+__global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const double *part_d, int nbd) {
   if (c->ddone) return;
-  __shared__ double red[5];
-  reduce_parts(part, nb, 5, red);
+  __shared__ double red[1];
+  __shared__ double rd[3];
+  reduce_parts(part_s, nbs, 1, red);
+  reduce_parts(part_d, nbd, 3, rd);
   if (threadIdx.x) return;
-  const double dAd = red[0], xAd = red[1], dAx = red[2], xd = red[3], dd = red[4];
+  const double dAd = red[0], dAx = rd[0], xd = rd[1], dd = rd[2];
   const double xAx = c->dxAx, xx = c->dxx;
-  const double bA = 0.5 * (xAd + dAx);  // symmetric A: both equal d^T A x
+  const double bA = dAx;  // d^T A x
   // minimiser of q(x + a d): A2 a^2 + B2 a + C2 = 0 (closed form), the root with the smaller quotient
   const double A2 = dAd * xd - bA * dd, B2 = dAd * xx - xAx * dd, C2 = bA * xx - xAx * xd;
   double r1, r2;
@@ -678,6 +694,15 @@ __global__ void k_gather_d(int n, const int *map, const double *src, double *dst
   GRIDLOOP(q, n) dst[q] = src[map[q]];
 }
 
+// values of a block schedule: dst[q] = src[map[q]] (0 where map < 0), in precision T
+template <typename T>
+__global__ void k_gather_blk(int m, const int *map, const double *src, T *dst) {
+  GRIDLOOP(q, m) {
+    const int j = map[q];
+    dst[q] = j >= 0 ? (T)src[j] : T(0);
+  }
+}
+
 // ============================================================== output helpers
 __global__ void k_absmax(int n, const double *v, double *part) {
   double m = 0.0;
@@ -772,10 +797,24 @@ struct bnx_ctx {
   int *rp = nullptr, *ci = nullptr;
   double *val = nullptr;
   float *val32 = nullptr;
+  // SELL-64 copy of A (when its padding is modest)
+  int *ell_ptr = nullptr, *ell_len = nullptr, *ell_col = nullptr, *ell_map = nullptr;
+  double *ell_v64 = nullptr;
+  float *ell_v32 = nullptr;
+  int ell_size = 0;
   int *Lrp = nullptr, *Lci = nullptr, *mapL = nullptr, *Ltrp = nullptr, *Ltci = nullptr, *mapLt = nullptr;
   int *levL = nullptr, *levLt = nullptr;
   double *Lv = nullptr, *Ltv = nullptr;
   float *Lv32 = nullptr, *Ltv32 = nullptr;
+  // block schedules of the LDS-staged solve: [0] forward (L), [1] backward (L^T); per precision
+  struct BlkDev {
+    int n = 0, B = 0, nblocks = 0, ell = 0;
+    int *perm = nullptr, *slot = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
+    int *valmap = nullptr, *diagmap = nullptr;
+    double *diag64 = nullptr, *val64 = nullptr;
+    float *diag32 = nullptr, *val32 = nullptr;
+  } blk[2][2];  // [direction][0 = fp64 block size, 1 = fp32 block size]
+  double *blk_rhs = nullptr;  // n doubles: right-hand side of a block solve in solve order
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -851,6 +890,12 @@ Mat<double> bnx_ctx::mat<double>() const {
   M.ci = ci;
   M.v = val;
   M.group = group;
+  if (ell_ptr) {
+    M.ell_ptr = ell_ptr;
+    M.ell_len = ell_len;
+    M.ell_col = ell_col;
+    M.ell_val = ell_v64;
+  }
   return M;
 }
 template <>
@@ -861,11 +906,31 @@ Mat<float> bnx_ctx::mat<float>() const {
   M.ci = ci;
   M.v = val32;
   M.group = group;
+  if (ell_ptr) {
+    M.ell_ptr = ell_ptr;
+    M.ell_len = ell_len;
+    M.ell_col = ell_col;
+    M.ell_val = ell_v32;
+  }
   return M;
 }
 template <>
 Tri<double> bnx_ctx::tri<double>(bool lower) const {
   Tri<double> F;
+  {
+    const BlkDev &b = blk[lower ? 0 : 1][0];
+    F.blk.n = b.n;
+    F.blk.B = b.B;
+    F.blk.nblocks = b.nblocks;
+    F.blk.perm = b.perm;
+    F.blk.slot = b.slot;
+    F.blk.slice_ptr = b.slice_ptr;
+    F.blk.slice_nnz = b.slice_nnz;
+    F.blk.ref = b.ref;
+    F.blk.diag = b.diag64;
+    F.blk.val = b.val64;
+  }
+  F.blk_scratch = blk_rhs;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -881,6 +946,20 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
 template <>
 Tri<float> bnx_ctx::tri<float>(bool lower) const {
   Tri<float> F;
+  {
+    const BlkDev &b = blk[lower ? 0 : 1][1];
+    F.blk.n = b.n;
+    F.blk.B = b.B;
+    F.blk.nblocks = b.nblocks;
+    F.blk.perm = b.perm;
+    F.blk.slot = b.slot;
+    F.blk.slice_ptr = b.slice_ptr;
+    F.blk.slice_nnz = b.slice_nnz;
+    F.blk.ref = b.ref;
+    F.blk.diag = b.diag32;
+    F.blk.val = b.val32;
+  }
+  F.blk_scratch = blk_rhs;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -915,8 +994,8 @@ int comb(bnx_ctx *C, T *out, const T *b0, double cb0c, const double *cb0d, const
   if (nd == 0)
     hipLaunchKernelGGL((k_comb<T, 0>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1, nt, V,
                        coef, sgn, 0, W, part, gate);
-  else if (nd <= 2)
-    hipLaunchKernelGGL((k_comb<T, 2>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1, nt, V,
+  else if (nd <= 4)
+    hipLaunchKernelGGL((k_comb<T, 4>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1, nt, V,
                        coef, sgn, nd, W, part, gate);
   else
     hipLaunchKernelGGL((k_comb<T, kMaxQ + 1>), dim3(nb), dim3(kBlock), 0, C->st, C->n, out, b0, cb0c, cb0d, b1, cb1,
@@ -930,7 +1009,8 @@ struct Work {
   int n = 0, kmax = 0, pcap = 0;
   T *p, *ap, *s, *g, *t, *c0, *z, *u, *Au, *r, *x, *Ax, *d, *Ad, *dg;
   T *S[kMaxK], *R[kMaxK];
-  T *Qm;  // n x pcap mirror of converged vectors
+  T *Qm;   // n x pcap mirror of converged vectors
+  T *AQm;  // n x pcap: A times each of them
 };
 
 template <typename T>
@@ -947,11 +1027,12 @@ void make_work(bnx_ctx *C, Work<T> &w, int kmax, int pcap) {
     w.R[s] = C->alloc<T>(n);
   }
   w.Qm = C->alloc<T>(n * (size_t)std::max(pcap, 1));
+  w.AQm = C->alloc<T>(n * (size_t)std::max(pcap, 1));
 }
 
 template <typename T>
 void free_work(bnx_ctx *C, Work<T> &w) {
-  T *vecs[] = {w.p, w.ap, w.s, w.g, w.t, w.c0, w.z, w.u, w.Au, w.r, w.x, w.Ax, w.d, w.Ad, w.dg, w.Qm};
+  T *vecs[] = {w.p, w.ap, w.s, w.g, w.t, w.c0, w.z, w.u, w.Au, w.r, w.x, w.Ax, w.d, w.Ad, w.dg, w.Qm, w.AQm};
   for (T *v : vecs) C->release(v);
   for (int s = 0; s < w.kmax; s++) {
     C->release(w.S[s]);
@@ -995,8 +1076,8 @@ struct PcgParams {
 // Solves J s = sgn (I - QQ^T) r with J = (I-QQ^T)(A - theta I)(I-QQ^T); Q = m vectors; pairs S,R (k,
 // chronological; Gram blocks already in ctl).  u, Au: for the eigen-residual test (eigtest).
 template <typename T>
-void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VList<T> &Q, int k, const VList<T> &S,
-         const VList<T> &R, const T *u, const T *Au, T *s_out, int *its, int *reason) {
+void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VList<T> &Q, const VList<T> &AQ, int k,
+         const VList<T> &S, const VList<T> &R, const T *u, const T *Au, T *s_out, int *its, int *reason) {
   const Launch L = C->launch();
   const int n = C->n;
   const int *gate = &C->ctl->done;
@@ -1026,7 +1107,6 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
   VList<T> ly{}, lx{};
   ly.p[0] = w.p;
   lx.p[0] = w.p;
-  for (int q = 0; q < m; q++) ly.p[1 + q] = lx.p[1 + q] = Q.p[q];
   VList<T> mdX{}, mdY{};
   for (int s = 0; s < k; s++) {
     mdX.p[s] = R.p[s];
@@ -1048,10 +1128,15 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, R, nullptr, gate);
     int nbd = launch_multidot<T, T>(L, n, k + m + 1, mdX, mdY, area(L, 3), gate);
     hipLaunchKernelGGL(c_pcg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd);
-    hipLaunchKernelGGL((k_pcg_newp<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p, l > 0 ? 1 : 0);
+    if (2 * m <= 8)
+      hipLaunchKernelGGL((k_pcg_newp<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
+                         l > 0 ? 1 : 0, 2 * m, AQ, area(L, 8));
+    else
+      hipLaunchKernelGGL((k_pcg_newp<T, 2 * kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
+                         l > 0 ? 1 : 0, 2 * m, AQ, area(L, 8));
     // y = J p
-    int nbs = launch_spmv<T>(L, A, w.p, w.ap, m + 1, ly, m + 1, lx, area(L, 0), gate);
-    hipLaunchKernelGGL(c_pcg_gamma, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbs);
+    int nbs = launch_spmv<T>(L, A, w.p, w.ap, 1, ly, 1, lx, area(L, 0), gate);
+    hipLaunchKernelGGL(c_pcg_gamma, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbs, area(L, 8), nbi);
     if (Du <= 8)
       hipLaunchKernelGGL((k_pcg_update<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u, Au,
                          s_out, w.g, t, area(L, 1));
@@ -1138,7 +1223,6 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   mdY.p[nq] = w.c0;
   VList<T> ly{}, lx{};
   ly.p[0] = w.d;
-  ly.p[1] = w.x;
   lx.p[0] = w.Ax;
   lx.p[1] = w.x;
   lx.p[2] = w.d;
@@ -1159,9 +1243,10 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     int nbd = launch_multidot<T, T>(L, n, nq + 1, mdX, mdY, area(L, 3), gate);
     hipLaunchKernelGGL(c_dacg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd, nq);
     // d = -(c0 - Qt zQ) + beta d
-    comb<T>(C, w.d, w.c0, -1.0, nullptr, w.d, &c->beta, nq, Qt, c->zQ, 1.0, 0, VList<T>{}, nullptr, gate);
-    int nbs = launch_spmv<T>(L, A, w.d, w.Ad, 2, ly, 3, lx, area(L, 4), gate);
-    hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs);
+    // (dots of the new d with Ax, x and d itself)
+    int nbc = comb<T>(C, w.d, w.c0, -1.0, nullptr, w.d, &c->beta, nq, Qt, c->zQ, 1.0, 3, lx, area(L, 9), gate);
+    int nbs = launch_spmv<T>(L, A, w.d, w.Ad, 1, ly, 0, VList<T>{}, area(L, 4), gate);
+    hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs, area(L, 9), nbc);
     hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, area(L, 5));
     hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
     poll.post(gate);
@@ -1218,15 +1303,18 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
   const bool fp64 = std::is_same<T, double>::value;
   Work<T> w;
   make_work<T>(C, w, o.kmax, p);
+  std::unique_ptr<Work<double>> w64;  // double DACG for stall restarts of the mixed path
   struct Guard {
     bnx_ctx *C;
     Work<T> *w;
+    std::unique_ptr<Work<double>> *w64;
     std::vector<double *> extra;
     ~Guard() {
       free_work<T>(C, *w);
+      if (*w64) free_work<double>(C, **w64);
       for (double *q : extra) C->release(q);
     }
-  } guard{C, &w, {}};
+  } guard{C, &w, &w64, {}};
   auto dalloc = [&](size_t cnt) {
     double *q = C->alloc<double>(cnt);
     guard.extra.push_back(q);
@@ -1273,7 +1361,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     DevCtl h = C->readctl();
     double theta = h.otheta, rn = h.orn;
     std::deque<int> ring;  // chronological slots
-    int k = 0;
+    int k = 0, slow = 0, restarts = 0;
     while (rn > o.tol * theta && k < o.itmax) {
       const int m = j + 1;
       VList<T> Q = QtT;
@@ -1295,7 +1383,10 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
       P.eigtest = 1;
       int its = 0, why = 0;
       rT = fp64 ? (T *)r_old : w.r;
-      pcg<T>(C, w, P, rT, m, Q, kk, SL, RL, uT, AuT, w.s, &its, &why);
+      VList<T> AQ{};
+      for (int q = 0; q < j; q++) AQ.p[q] = w.AQm + (size_t)q * n;
+      AQ.p[j] = AuT;
+      pcg<T>(C, w, P, rT, m, Q, AQ, kk, SL, RL, uT, AuT, w.s, &its, &why);
       S.pcg_its[j] += its;
       S.mvp_newton += its;
       if (why == 4) S.pcg_breakdowns++;
@@ -1370,9 +1461,44 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
         hipLaunchKernelGGL(c_gram, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 6), nb, shift, insert ? 1 : 0, kn, j);
       }
       std::swap(r_old, r_new);
+      // stall: no PCG step, or the residual fails to drop below 0.9x twice in a row
+      slow = (its == 0 || h.orn > 0.9 * rn) ? slow + 1 : 0;
       theta = h.otheta;
       rn = h.orn;
       k++;
+      if ((its == 0 || slow >= 2) && restarts < 5 && rn > o.tol * theta && k < o.itmax) {
+        // the start was not close enough (Sec. 4.1): resume DACG from u with a tighter tolerance,
+        // restart the BFGS history, then continue Newton
+        const double td2 = now_s();
+        const double t2 = std::min(o.tol_dacg, std::max(o.tol, 0.1 * rn / theta));
+        long long mvp2 = 0;
+        if (fp64) {
+          launch_cast<double, T>(C->st, n, u, w.x);
+          S.dacg_its[j] += dacg<T>(C, w, j, QtT, t2, o.itmax_dacg, &mvp2);
+          launch_cast<T, double>(C->st, n, w.x, u);
+        } else {
+          // tolerances below the float residual floor need the double DACG
+          if (!w64) {
+            w64.reset(new Work<double>);
+            make_work<double>(C, *w64, 0, 0);
+          }
+          HIPCHK(hipMemcpyAsync(w64->x, u, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+          S.dacg_its[j] += dacg<double>(C, *w64, j, Qt64, t2, o.itmax_dacg, &mvp2);
+          HIPCHK(hipMemcpyAsync(u, w64->x, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+        }
+        S.mvp_dacg += mvp2;
+        cgs2_normalize(C, u, tmp, j, Qt64);
+        ring.clear();
+        outer_eval<T>(C, u, Au, r_old, fp64 ? nullptr : w.u, fp64 ? nullptr : w.Au, fp64 ? nullptr : w.r);
+        S.mvp_newton++;
+        h = C->readctl();
+        theta = h.otheta;
+        rn = h.orn;
+        restarts++;
+        S.dacg_restarts++;
+        slow = 0;
+        S.t_dacg += now_s() - td2;
+      }
     }
     S.outer_its[j] = k;
     S.relres[j] = rn / theta;
@@ -1380,6 +1506,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     lam[j] = theta;
     HIPCHK(hipMemcpyAsync(V64 + (size_t)j * n, u, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
     if (!fp64) launch_cast<double, T>(C->st, n, u, w.Qm + (size_t)j * n);
+    launch_cast<double, T>(C->st, n, Au, w.AQm + (size_t)j * n);  // A v_j from the last outer step
     C->sync();
     S.t_newton += now_s() - t0;
   }
@@ -1491,6 +1618,10 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
   if (!fp64)
     for (int q = 0; q < p; q++) launch_cast<double, T>(C->st, n, V + (size_t)q * n, w.Qm + (size_t)q * n);
   Mat<double> A64 = C->mat<double>();
+  for (int q = 0; q < p; q++) {  // A v_q for the projection coefficients of the adjoint PCG
+    launch_spmv<double>(L, A64, V + (size_t)q * n, tmp, 0, VList<double>{}, 0, VList<double>{}, nullptr, nullptr);
+    launch_cast<double, T>(C->st, n, tmp, w.AQm + (size_t)q * n);
+  }
   for (int i = 0; i < p; i++) {
     const double *G = g_evecs_dev + (size_t)i * n;
     if (!(norm2_host(C, G) > 0.0)) continue;
@@ -1509,8 +1640,11 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
       launch_fill<double>(C->st, n, xi, 0.0);
     }
     // eta in the complement of Q = [v_1..v_i]: (I-QQ^T)(A - lambda_i I)(I-QQ^T) eta = (I-QQ^T) G
-    VList<T> Q{};
-    for (int q = 0; q < m; q++) Q.p[q] = fp64 ? (const T *)(V + (size_t)q * n) : w.Qm + (size_t)q * n;
+    VList<T> Q{}, AQ{};
+    for (int q = 0; q < m; q++) {
+      Q.p[q] = fp64 ? (const T *)(V + (size_t)q * n) : w.Qm + (size_t)q * n;
+      AQ.p[q] = w.AQm + (size_t)q * n;
+    }
     project_out(C, rhs, G, m, Vl, tmp);
     const double rhs_n = norm2_host(C, rhs);
     launch_fill<double>(C->st, n, eta, 0.0);
@@ -1525,7 +1659,7 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
     if (fp64) {
       P.tol_pcg = C->adj_tol;
       int its = 0, why = 0;
-      pcg<T>(C, w, P, (const T *)res, m, Q, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, (T *)eta, &its, &why);
+      pcg<T>(C, w, P, (const T *)res, m, Q, AQ, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, (T *)eta, &its, &why);
     } else {
       // float PCG inside double iterative refinement
       P.tol_pcg = 1e-4;
@@ -1533,7 +1667,7 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
       for (int round = 0; round < 40 && resn > C->adj_tol * rhs_n; round++) {
         launch_cast<double, T>(C->st, n, res, w.r);
         int its = 0, why = 0;
-        pcg<T>(C, w, P, w.r, m, Q, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, w.s, &its, &why);
+        pcg<T>(C, w, P, w.r, m, Q, AQ, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, w.s, &its, &why);
         launch_cast<T, double>(C->st, n, w.s, tmp);
         // eta += delta  (coefficient 1 via scal[0])
         hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal, 1.0);
@@ -1609,6 +1743,21 @@ void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
   hipLaunchKernelGGL(k_gather_d, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapLt, C->Lv, C->Ltv);
   launch_cast<double, float>(C->st, nnzL, C->Lv, C->Lv32);
   launch_cast<double, float>(C->st, nnzL, C->Ltv, C->Ltv32);
+  for (int dir = 0; dir < 2; dir++) {
+    const double *src = dir == 0 ? C->Lv : C->Ltv;
+    for (int pr = 0; pr < 2; pr++) {
+      auto &b = C->blk[dir][pr];
+      if (pr == 0) {
+        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src, b.diag64);
+        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
+                           b.val64);
+      } else {
+        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src, b.diag32);
+        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
+                           b.val32);
+      }
+    }
+  }
   C->sync();
   C->t_factor = now_s() - t0;
   C->factored = true;
@@ -1636,6 +1785,12 @@ void upload_values(bnx_ctx *C, const double *val) {
   HIPCHK(hipMemcpyAsync(C->val, val, sizeof(double) * C->nnz,
                         C->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, C->st));
   launch_cast<double, float>(C->st, C->nnz, C->val, C->val32);
+  if (C->ell_ptr) {
+    hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(C->ell_size)), dim3(kBlock), 0, C->st, C->ell_size,
+                       C->ell_map, C->val, C->ell_v64);
+    hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(C->ell_size)), dim3(kBlock), 0, C->st, C->ell_size,
+                       C->ell_map, C->val, C->ell_v32);
+  }
   // diagonal must be positive
   std::vector<double> hv(C->nnz);
   HIPCHK(hipMemcpyAsync(hv.data(), C->val, sizeof(double) * C->nnz, hipMemcpyDeviceToHost, C->st));
@@ -1717,7 +1872,8 @@ static void prec_apply_t(bnx_ctx *C, int k, const double *S, const double *R, in
   mY.p[k + m] = w.c0;
   nb = launch_multidot<T, T>(L, n, k + m + 1, mX, mY, area(L, 3), nullptr);
   hipLaunchKernelGGL(c_pcg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nb);
-  hipLaunchKernelGGL((k_pcg_newp<T>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, c, w.c0, k, SL, m, QL, w.p, 0);
+  hipLaunchKernelGGL((k_pcg_newp<T, 0>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, c, w.c0, k, SL, m, QL, w.p, 0, 0,
+                     VList<T>{}, nullptr);
   launch_cast<T, double>(C->st, n, w.p, out);
   DevCtl h = C->readctl();
   free_work<T>(C, w);
@@ -1748,6 +1904,12 @@ static void corr_solve_t(bnx_ctx *C, int m, const double *Q, int k, const double
     QL.p[q] = w.Qm + (size_t)q * n;
   }
   gram_full<T>(C, k, SL, RL, m, QL);
+  VList<T> AQ{};
+  for (int q = 0; q < m; q++) {
+    launch_spmv<T>(C->launch(), C->mat<T>(), QL.p[q], w.AQm + (size_t)q * n, 0, VList<T>{}, 0, VList<T>{}, nullptr,
+                   nullptr);
+    AQ.p[q] = w.AQm + (size_t)q * n;
+  }
   PcgParams P;
   P.theta = theta;
   P.tol_pcg = tol_pcg;
@@ -1757,7 +1919,7 @@ static void corr_solve_t(bnx_ctx *C, int m, const double *Q, int k, const double
   P.xi = xi;
   P.sgn = -1.0;
   P.eigtest = 1;
-  pcg<T>(C, w, P, w.r, m, QL, k, SL, RL, w.u, w.Au, w.s, its, reason);
+  pcg<T>(C, w, P, w.r, m, QL, AQ, k, SL, RL, w.u, w.Au, w.s, its, reason);
   launch_cast<T, double>(C->st, n, w.s, s);
   C->sync();
   C->release(u);
@@ -1848,13 +2010,44 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     if (!v.empty()) throw ApiError{BNX_E_ARG, v};
     analyse(C->an);
     C->group = spmv_group((double)nnz / (double)n);
+    for (int dir = 0; dir < 2; dir++)
+      for (int pr = 0; pr < 2; pr++) {
+        BlockSched bs;
+        block_schedule(C->an, dir == 0, block_rows_for(pr == 0 ? 8 : 4), bs);
+        auto &b = C->blk[dir][pr];
+        b.n = bs.n;
+        b.B = bs.B;
+        b.nblocks = bs.nblocks;
+        b.ell = bs.ell;
+        auto up = [&](const std::vector<int> &v) {
+          int *d = C->alloc<int>(v.size());
+          HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
+          return d;
+        };
+        b.perm = up(bs.perm);
+        b.slot = up(bs.slot);
+        b.slice_ptr = up(bs.slice_ptr);
+        b.slice_nnz = up(bs.slice_nnz);
+        b.ref = up(bs.ref);
+        b.valmap = up(bs.valmap);
+        b.diagmap = up(bs.diagmap);
+        if (pr == 0) {
+          b.diag64 = C->alloc<double>(n);
+          b.val64 = C->alloc<double>(std::max(bs.ell, 1));
+        } else {
+          b.diag32 = C->alloc<float>(n);
+          b.val32 = C->alloc<float>(std::max(bs.ell, 1));
+        }
+        C->sync();  // host vectors go out of scope
+      }
     if (const char *e = getenv("BNX_SF_WAVES")) C->sf_waves = atoi(e);  // tuning override of the solve window
     C->rp = C->alloc<int>(n + 1);
     C->ci = C->alloc<int>(nnz);
     C->val = C->alloc<double>(nnz);
     C->val32 = C->alloc<float>(nnz);
     C->ctl = C->alloc<DevCtl>(1);
-    C->part = C->alloc<double>((size_t)8 * kPartSlots * kNBMax);
+    C->blk_rhs = C->alloc<double>(n);
+    C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
     C->dflag = C->alloc<int>(4);
     HIPCHK(hipHostMalloc((void **)&C->hctl, sizeof(DevCtl), hipHostMallocDefault));
@@ -1977,7 +2170,7 @@ bnx_status bnx_kernel_time(bnx_ctx *C, int kernel, double *ms_total, long long *
 }
 
 bnx_status bnx_set_trsv_mode(bnx_ctx *C, int mode) {
-  if (!C || (mode != 0 && mode != 1)) return BNX_E_ARG;
+  if (!C || mode < 0 || mode > 2) return BNX_E_ARG;
   C->trsv_mode = mode;
   return BNX_OK;
 }

@@ -45,6 +45,8 @@ def mats():
             "diffusion_12": W.diffusion_3d(12, seed=1),
             "elasticity_3": W.elasticity_q1(3, seed=2),
             "rgg_3000": W.rgg_laplacian(3000, seed=3),
+            "diffusion_40": W.diffusion_3d(40, seed=1),  # several LDS blocks per solve
+            "rgg_60000": W.rgg_laplacian(60000, seed=3),
         }
     return _CACHE["m"]
 
@@ -80,8 +82,9 @@ def test_spmv(oracle_mod, name):
 
 
 # ----------------------------------------------------------------------------- a0, a5, a6: IC(0) and the solves
-@pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("name", ["laplace2d_32", "diffusion_12", "elasticity_3", "rgg_3000"])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("name", ["laplace2d_32", "diffusion_12", "elasticity_3", "rgg_3000", "diffusion_40",
+                                  "rgg_60000"])
 def test_ic_solves(oracle_mod, name, mode):
     A = mats()[name]
     say("case ic", name, "mode", mode)
@@ -255,7 +258,7 @@ def test_solve_laplace2d_closed_form(oracle_mod):
     S.close()
 
 
-@pytest.mark.parametrize("name,p", [("diffusion_12", 6), ("elasticity_3", 5), ("rgg_3000", 3)])
+@pytest.mark.parametrize("name,p", [("diffusion_12", 6), ("elasticity_3", 5), ("rgg_3000", 3), ("diffusion_40", 3)])
 def test_solve_matches_oracle(oracle_mod, name, p):
     A = mats()[name]
     x0 = W.initial_block(A.n, p, 0)
