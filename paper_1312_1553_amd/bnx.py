@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libbnx.so")
+LIBPATH = os.environ.get("BNX_LIBPATH") or os.path.join(HERE, "libbnx.so")
 MAX_P = 32
 FP64, MIXED = 0, 1
 

@@ -148,23 +148,25 @@ void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs) {
   }
   // sort each block by (level, position)
   bs.perm.assign(n, 0);
-  bs.slot.assign(n, 0);
   bs.diagmap.assign(n, 0);
-  std::vector<int> order;
+  std::vector<int> rank(n, 0), order;
   for (int b = 0; b < bs.nblocks; b++) {
     const int p0 = b * B, p1 = std::min(n, p0 + B);
     order.resize(p1 - p0);
     for (int p = p0; p < p1; p++) order[p - p0] = p;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return llev[a] < llev[c]; });
     for (int k = p0; k < p1; k++) {
-      const int p = order[k - p0];
-      const int i = row_at(p);
+      const int i = row_at(order[k - p0]);
       bs.perm[k] = i;
-      bs.slot[k] = p - p0;
+      rank[i] = k;
       bs.diagmap[k] = lower ? rp[i + 1] - 1 : rp[i];
     }
   }
-  // ELL slices of 64 sorted rows
+  // first kNR dependencies per rank, rank-indexed
+  bs.cnt.assign(n, 0);
+  bs.ref4.assign((size_t)kNR * n, INT32_MIN);
+  bs.valmap4.assign((size_t)kNR * n, -1);
+  // ELL slices of 64 ranks for the dependencies beyond kNR
   bs.nslices = (n + 63) / 64;
   bs.slice_ptr.assign(bs.nslices + 1, 0);
   bs.slice_nnz.assign(bs.nslices, 0);
@@ -172,7 +174,7 @@ void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs) {
     int mx = 0;
     for (int k = sl * 64; k < std::min(n, sl * 64 + 64); k++) {
       const int i = bs.perm[k];
-      mx = std::max(mx, rp[i + 1] - rp[i] - 1);
+      mx = std::max(mx, rp[i + 1] - rp[i] - 1 - kNR);
     }
     bs.slice_nnz[sl] = mx;
     bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * mx;
@@ -183,15 +185,21 @@ void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs) {
   for (int k = 0; k < n; k++) {
     const int sl = k / 64, lane = k % 64;
     const int i = bs.perm[k];
-    const int b0 = (k / B) * B;  // block start (sorted index == position range start)
+    const int b0 = (k / B) * B;  // first rank of the block
     const int e0 = lower ? rp[i] : rp[i] + 1, e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
+    bs.cnt[k] = e1 - e0;
     int e = 0;
     for (int q = e0; q < e1; q++, e++) {
-      const int j = ci[q];
-      const int pj = pos_of(j);
-      const int at = bs.slice_ptr[sl] + 64 * e + lane;
-      bs.ref[at] = (pj >= b0) ? -(pj - b0) - 1 : j;
-      bs.valmap[at] = q;
+      const int kj = rank[ci[q]];
+      const int r = (kj >= b0) ? -(kj - b0) - 1 : kj;
+      if (e < kNR) {
+        bs.ref4[(size_t)e * n + k] = r;
+        bs.valmap4[(size_t)e * n + k] = q;
+      } else {
+        const int at = bs.slice_ptr[sl] + 64 * (e - kNR) + lane;
+        bs.ref[at] = r;
+        bs.valmap[at] = q;
+      }
     }
   }
 }

@@ -63,18 +63,24 @@ struct Levels {
 // dependency has a smaller position), cut into blocks of B consecutive
 // positions, and each block is sorted by the rows' level in the whole
 // dependency graph, so that all blocks advance through the levels together and
-// the rows a block needs from earlier blocks are produced early.  Sorted index k = block start + rank in block.
-// Row data is stored as 64-row ELL slices: entry e of lane l of slice s is at
-// slice_ptr[s] + 64 e + l; ref >= 0 is an external dependency (global row id),
-// ref < 0 an in-block one (LDS slot -ref-1); padding has ref = INT_MIN.
+// the rows a block needs from earlier blocks are produced early.  A row's rank
+// k is its index in that order (block b holds ranks b*B .. b*B+B-1).
+// The first kNR dependencies of rank k are at [q * n + k] (q < kNR) of ref4 /
+// valmap4; further ones of long rows are stored as 64-row ELL slices: entry
+// e >= kNR of lane l of slice s is at slice_ptr[s] + 64 (e - kNR) + l.
+// ref >= 0 is an external dependency (its global rank), ref < 0 an in-block
+// one (local rank -ref-1); unused entries have ref = INT_MIN.
+constexpr int kNR = 4;
 struct BlockSched {
   int n = 0, B = 0, nblocks = 0, nslices = 0, ell = 0;
   int max_local_levels = 0;
-  std::vector<int> perm;       // n: original row of sorted index k
-  std::vector<int> slot;       // n: LDS slot (position - block start) of sorted index k
+  std::vector<int> perm;       // n: original row of rank k
   std::vector<int> diagmap;    // n: factor value index of the diagonal of row perm[k]
+  std::vector<int> cnt;        // n: number of dependencies of rank k
+  std::vector<int> ref4;       // kNR * n
+  std::vector<int> valmap4;    // kNR * n, -1 where unused
   std::vector<int> slice_ptr;  // nslices+1
-  std::vector<int> slice_nnz;  // nslices
+  std::vector<int> slice_nnz;  // nslices: entries beyond kNR
   std::vector<int> ref;        // ell entries
   std::vector<int> valmap;     // ell entries: factor value index, -1 for padding
 };
@@ -116,14 +122,16 @@ struct Mat {
 template <typename T>
 struct DevBlk {
   int n = 0, B = 0, nblocks = 0;
-  const int *perm = nullptr, *slot = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
-  const T *diag = nullptr, *val = nullptr;
+  const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
+  const int *cnt = nullptr, *ref4 = nullptr;
+  const T *diag = nullptr, *val = nullptr, *val4 = nullptr;  // diag holds reciprocals
 };
 
 template <typename T>
 struct Tri {
   DevBlk<T> blk;
   void *blk_scratch = nullptr;  // n values: right-hand side in solve order
+  void *blk_xr = nullptr;       // n values: solution in solve order (polled by later blocks)
   int n = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;

@@ -300,6 +300,20 @@ __global__ void k_sentinel(size_t n, T *x, int *counter, const int *gate) {
 }
 
 constexpr int kSpinLimit = 1 << 20;
+// Block solve polling: LDS polling rounds between examinations of the external
+// polls, and the s_sleep issued after a polling round without progress.
+#ifndef BNX_TRSV_ILIM
+#define BNX_TRSV_ILIM 2
+#endif
+#ifndef BNX_TRSV_SLEEP
+#define BNX_TRSV_SLEEP 0
+#endif
+#ifndef BNX_TRSV_WC
+#define BNX_TRSV_WC 12
+#endif
+#ifndef BNX_TRSV_PUBSLEEP
+#define BNX_TRSV_PUBSLEEP 1
+#endif
 
 // Sync-free solve: a persistent grid of waves takes chunks of 64 rows in level
 // order from a counter; a lane owns one row, consumes its dependencies as they
@@ -370,15 +384,15 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
 // from the global solution, both polled until they leave the sentinel state.
 // Each wave walks its 64-row slices of the block in order (rows sorted by local
 // level), so a lane only waits on rows of lower rank, which finish first.
-// Right-hand side in solve order and sentinel fill:  bp[k] = b[perm[k]] - sum_t coef[t] R_t[perm[k]],
-// x[i] = sentinel, counter = 0.  Makes every per-row load of the solve a rank-indexed (coalesced) load.
+// Right-hand side in solve order and sentinel fill of the rank-ordered solution:
+//   bp[k] = b[perm[k]] - sum_t coef[t] R_t[perm[k]],  xr[k] = sentinel,  counter = 0.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_trsv_prep(int n, const int *__restrict__ perm, const T *__restrict__ b,
-                                                      int kfuse, VList<T> R, const double *coef, T *bp, T *x,
+                                                      int kfuse, VList<T> R, const double *coef, T *bp, T *xr,
                                                       int *counter, const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
-  U *xu = reinterpret_cast<U *>(x);
+  U *xu = reinterpret_cast<U *>(xr);
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
     bp[k] = rhs_value(perm[k], b, kfuse, R, coef);
     xu[k] = Sentinel<T>::bits;
@@ -388,38 +402,49 @@ __global__ __launch_bounds__(kBlock) void k_trsv_prep(int n, const int *__restri
 
 template <typename T, int NR>
 struct RowPre {
-  int row, my, sp, nz;
+  int cnt;
   T d, s;
   int rr[NR];
   T vv[NR];
 };
 
+// Row data of rank base+lane (all loads rank-indexed and independent of each other).
 template <typename T, int NR>
 __device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int base, int k1, int lane,
                                           RowPre<T, NR> &R) {
   const int k = base + lane;
-  const int sl = base >> 6;
-  R.nz = F.slice_nnz[sl];
-  R.sp = F.slice_ptr[sl] + lane;
   const bool ok = k < k1;
-  R.row = ok ? F.perm[k] : 0;
-  R.my = ok ? F.slot[k] : 0;
-  R.d = ok ? F.diag[k] : T(1);
+  const int n = F.n;
+  R.cnt = ok ? F.cnt[k] : 0;
+  R.d = ok ? F.diag[k] : T(1);  // reciprocal of the diagonal
   R.s = ok ? bp[k] : T(0);
 #pragma unroll
   for (int q = 0; q < NR; q++) {
-    const bool has = ok && q < R.nz;
-    R.rr[q] = has ? F.ref[R.sp + 64 * q] : INT32_MIN;
-    R.vv[q] = has ? F.val[R.sp + 64 * q] : T(0);
+    R.rr[q] = ok ? F.ref4[(size_t)q * n + k] : INT32_MIN;
+    R.vv[q] = ok ? F.val4[(size_t)q * n + k] : T(0);
   }
 }
 
+// LDS-staged sync-free solve.  One 1024-thread workgroup per block of B ranks
+// (blocks taken in order from a ticket counter); the block's solution lives in
+// LDS, indexed by local rank.
+//  * 12 compute waves walk the block's 64-row slices in order (wave w takes
+//    slices w, w+12, ...).  A lane resolves its row's dependencies from LDS
+//    (in-block) or by polling the rank-ordered global solution xr (earlier
+//    blocks), and writes its result to LDS only, so compute waves never wait
+//    on their own stores.
+//  * 4 publisher waves copy finished LDS values to xr (coalesced, for later
+//    blocks) and to the output x (original order).
+// Every dependency has a lower rank, so the lowest unfinished row can always
+// proceed.  Waits are bounded: on overflow the value becomes NaN and *err is set.
 template <typename T, int B>
-__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, int *counter,
+__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xr, int *counter,
                                                     int *err, const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
-  constexpr int NR = 4;  // dependencies cached in registers per row
+  constexpr int NR = kNR;  // dependencies cached in registers per row
+  constexpr int WC = BNX_TRSV_WC;  // compute waves
+  constexpr int WP = 16 - WC;
   __shared__ U xs[B];
   __shared__ int blk_s;
   if (threadIdx.x == 0) blk_s = atomicAdd(counter, 1);
@@ -427,24 +452,51 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   __syncthreads();
   const int blk = blk_s;
   if (blk >= F.nblocks) return;
+  U *xru = reinterpret_cast<U *>(xr);
   U *xu = reinterpret_cast<U *>(x);
   const int n = F.n;
   const int k0 = blk * B, k1 = (k0 + B < n) ? k0 + B : n;
+  const int nsl = (k1 - k0 + 63) >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int base = k0 + wave * 64;
-  RowPre<T, NR> cur, nxt;
-  if (base < k1) row_fetch<T, NR>(F, bp, base, k1, lane, nxt);
-  for (; base < k1; base += 1024) {
-    cur = nxt;
-    // prefetch the next round while this one waits for its dependencies
-    if (base + 1024 < k1) row_fetch<T, NR>(F, bp, base + 1024, k1, lane, nxt);
+
+  if (wave >= WC) {  // publisher
+    for (int sl = wave - WC; sl < nsl; sl += WP) {
+      const int t = (sl << 6) + lane;
+      const int k = k0 + t;
+      if (k < k1) {
+        const int row = F.perm[k];
+        U u;
+        int spins = 0;
+        while ((u = __hip_atomic_load(&xs[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == Sentinel<T>::bits) {
+          if (++spins > kSpinLimit) {
+            u = to_bits<T>(T(__builtin_nan("")));
+            atomicOr(err, 1);
+            break;
+          }
+          if (BNX_TRSV_PUBSLEEP > 0) __builtin_amdgcn_s_sleep(BNX_TRSV_PUBSLEEP);
+        }
+        __hip_atomic_store(&xru[k], u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        xu[row] = u;
+      }
+    }
+    return;
+  }
+
+  // two rounds of row data in flight ahead of the current one
+  RowPre<T, NR> cur, nx1, nx2;
+  if (wave < nsl) row_fetch<T, NR>(F, bp, k0 + (wave << 6), k1, lane, nx1);
+  if (wave + WC < nsl) row_fetch<T, NR>(F, bp, k0 + ((wave + WC) << 6), k1, lane, nx2);
+  for (int sl = wave; sl < nsl; sl += WC) {
+    const int base = k0 + (sl << 6);
+    cur = nx1;
+    nx1 = nx2;
+    if (sl + 2 * WC < nsl) row_fetch<T, NR>(F, bp, k0 + ((sl + 2 * WC) << 6), k1, lane, nx2);
+    const int t = base - k0 + lane;
     bool fin = base + lane >= k1;
-    int nown = 0;
-#pragma unroll
-    for (int q = 0; q < NR; q++)
-      if (cur.rr[q] != INT32_MIN) nown = q + 1;
-    const int nlong = (!fin && cur.nz > NR) ? cur.nz : NR;  // entries beyond the register cache
-    // masks of cached dependencies: in-block (LDS) and external (global)
+    const int nown = cur.cnt < NR ? cur.cnt : NR;
+    const int nlong = cur.cnt;  // entries beyond NR come from the ELL slices
+    const int gsl = base >> 6;
+    const int esp = nlong > NR ? F.slice_ptr[gsl] + lane : 0;
     unsigned need_l = 0, need_g = 0;
 #pragma unroll
     for (int q = 0; q < NR; q++) {
@@ -461,81 +513,83 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     T s = cur.s;
     int e = NR, spins = 0;
     while (!fin) {
-      // 1) global polls for external dependencies: issued now, examined after the LDS phase
+      // 1) polls of external dependencies, examined after the LDS phase (skipped by the
+      //    whole wave when no lane has one pending, so no memory wait is needed then)
+      const bool gpend = (need_g & ~seen) != 0u;
+      const bool anyg = __builtin_amdgcn_ballot_w64(gpend) != 0ull;
       U gv[NR];
+      if (anyg) {
 #pragma unroll
-      for (int q = 0; q < NR; q++)
-        gv[q] = ((need_g & ~seen) >> q & 1u)
-                    ? __hip_atomic_load(&xu[cur.rr[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                    : Sentinel<T>::bits;
-      // 2) LDS phase: spin on in-block dependencies; a row whose dependencies are all in finishes here
-      for (int it = 0; it < 64 && !fin && (need_l & ~seen); it++, spins++) {
+        for (int q = 0; q < NR; q++)
+          gv[q] = ((need_g & ~seen) >> q & 1u)
+                      ? __hip_atomic_load(&xru[cur.rr[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                      : Sentinel<T>::bits;
+      }
+      // 2) LDS phase; a row whose dependencies have all arrived finishes here
+      for (int it = 0; it < BNX_TRSV_ILIM && !fin && (need_l & ~seen); it++, spins++) {
+        const unsigned pend = need_l & ~seen;
+        U lv[NR];
 #pragma unroll
-        for (int q = 0; q < NR; q++) {
-          if ((need_l & ~seen) >> q & 1u) {
-            const U u = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (u != Sentinel<T>::bits) {
-              xv[q] = from_bits<T>(u);
-              seen |= 1u << q;
-            }
+        for (int q = 0; q < NR; q++)  // all LDS polls issued before any result is examined
+          lv[q] = (pend >> q & 1u)
+                      ? __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                      : Sentinel<T>::bits;
+#pragma unroll
+        for (int q = 0; q < NR; q++)
+          if ((pend >> q & 1u) && lv[q] != Sentinel<T>::bits) {
+            xv[q] = from_bits<T>(lv[q]);
+            seen |= 1u << q;
           }
-        }
-        if (seen == (need_l | need_g) && nlong == NR) {
+        if (BNX_TRSV_SLEEP > 0 && (need_l & ~seen) == pend) __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
+        if (seen == (need_l | need_g) && nlong <= NR) {
 #pragma unroll
           for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
-          const U v = to_bits<T>(s / cur.d);
-          __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           fin = true;
         }
       }
       if (fin) break;
-      // 3) results of the global polls
+      // 3) results of the external polls
+      if (anyg) {
 #pragma unroll
-      for (int q = 0; q < NR; q++)
-        if (((need_g & ~seen) >> q & 1u) && gv[q] != Sentinel<T>::bits) {
-          xv[q] = from_bits<T>(gv[q]);
-          seen |= 1u << q;
-        }
+        for (int q = 0; q < NR; q++)
+          if (((need_g & ~seen) >> q & 1u) && gv[q] != Sentinel<T>::bits) {
+            xv[q] = from_bits<T>(gv[q]);
+            seen |= 1u << q;
+          }
+      }
       if (seen == (need_l | need_g)) {
         if (!cached_done) {
 #pragma unroll
           for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
           cached_done = true;
         }
-        // rows longer than the register cache: the rest in order
+        // rows longer than the register cache: the remaining entries in order
         bool blocked = false;
         while (e < nlong) {
-          const int r = F.ref[cur.sp + 64 * e];
-          if (r == INT32_MIN) {
-            e = nlong;
-            break;
-          }
+          const int at = esp + 64 * (e - NR);
+          const int r = F.ref[at];
           const U u = r < 0 ? __hip_atomic_load(&xs[-r - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                            : __hip_atomic_load(&xu[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            : __hip_atomic_load(&xru[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (u == Sentinel<T>::bits) {
             blocked = true;
             break;
           }
-          s -= F.val[cur.sp + 64 * e] * from_bits<T>(u);
+          s -= F.val[at] * from_bits<T>(u);
           e++;
         }
         if (!blocked) {
-          const U v = to_bits<T>(s / cur.d);
-          __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           fin = true;
           break;
         }
       }
       if (++spins > kSpinLimit) {
-        const U v = to_bits<T>(T(__builtin_nan("")));
-        __hip_atomic_store(&xs[cur.my], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_store(&xu[cur.row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         atomicOr(err, 1);
         fin = true;
       } else if (!(need_l & ~seen)) {
-        __builtin_amdgcn_s_sleep(1);  // only global dependencies left
+        __builtin_amdgcn_s_sleep(1);  // only external dependencies left
       }
     }
   }
@@ -557,8 +611,8 @@ int block_rows_for(int elem_bytes) {
 }
 
 template <typename T, int B>
-static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  hipLaunchKernelGGL((k_trsv_blk<T, B>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, L.counter,
+static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, T *xr, const int *gate) {
+  hipLaunchKernelGGL((k_trsv_blk<T, B>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, xr, L.counter,
                      &L.ctl->err, gate);
 }
 
@@ -569,16 +623,17 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
     const bool prof0 = L.prof && L.prof->on;
     hipEvent_t ev0 = nullptr;
     T *bp = reinterpret_cast<T *>(F.blk_scratch);
+    T *xr = reinterpret_cast<T *>(F.blk_xr);
     hipLaunchKernelGGL((k_trsv_prep<T>), dim3(grid_for(F.n, kNBMax)), dim3(kBlock), 0, L.st, F.n, F.blk.perm, b, kfuse,
-                       R, coef, bp, x, L.counter, gate);
+                       R, coef, bp, xr, L.counter, gate);
     if (prof0) L.prof->begin(L.st, &ev0);
     switch (F.blk.B) {
-      case 1024: launch_blk<T, 1024>(L, F, bp, x, gate); break;
-      case 2048: launch_blk<T, 2048>(L, F, bp, x, gate); break;
-      case 4096: launch_blk<T, 4096>(L, F, bp, x, gate); break;
-      case 8192: launch_blk<T, 8192>(L, F, bp, x, gate); break;
-      case 16384: launch_blk<T, 16384>(L, F, bp, x, gate); break;
-      default: launch_blk<T, blk_rows<T>()>(L, F, bp, x, gate); break;
+      case 1024: launch_blk<T, 1024>(L, F, bp, x, xr, gate); break;
+      case 2048: launch_blk<T, 2048>(L, F, bp, x, xr, gate); break;
+      case 4096: launch_blk<T, 4096>(L, F, bp, x, xr, gate); break;
+      case 8192: launch_blk<T, 8192>(L, F, bp, x, xr, gate); break;
+      case 16384: launch_blk<T, 16384>(L, F, bp, x, xr, gate); break;
+      default: launch_blk<T, blk_rows<T>()>(L, F, bp, x, xr, gate); break;
     }
     if (prof0) L.prof->end(L.st, (F.lower ? 2 : 4) + (sizeof(T) == 8 ? 0 : 1), ev0);
     return;

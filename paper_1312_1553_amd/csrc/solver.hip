@@ -703,6 +703,12 @@ __global__ void k_gather_blk(int m, const int *map, const double *src, T *dst) {
   }
 }
 
+// reciprocal diagonal of a block schedule: dst[k] = 1 / src[map[k]] (rounded once, in double)
+template <typename T>
+__global__ void k_gather_rdiag(int m, const int *map, const double *src, T *dst) {
+  GRIDLOOP(q, m) dst[q] = (T)(1.0 / src[map[q]]);
+}
+
 // ============================================================== output helpers
 __global__ void k_absmax(int n, const double *v, double *part) {
   double m = 0.0;
@@ -809,12 +815,13 @@ struct bnx_ctx {
   // block schedules of the LDS-staged solve: [0] forward (L), [1] backward (L^T); per precision
   struct BlkDev {
     int n = 0, B = 0, nblocks = 0, ell = 0;
-    int *perm = nullptr, *slot = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
-    int *valmap = nullptr, *diagmap = nullptr;
-    double *diag64 = nullptr, *val64 = nullptr;
-    float *diag32 = nullptr, *val32 = nullptr;
+    int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
+    int *valmap = nullptr, *diagmap = nullptr, *cnt = nullptr, *ref4 = nullptr, *valmap4 = nullptr;
+    double *diag64 = nullptr, *val64 = nullptr, *val4_64 = nullptr;
+    float *diag32 = nullptr, *val32 = nullptr, *val4_32 = nullptr;
   } blk[2][2];  // [direction][0 = fp64 block size, 1 = fp32 block size]
   double *blk_rhs = nullptr;  // n doubles: right-hand side of a block solve in solve order
+  double *blk_xr = nullptr;   // n doubles: its solution in solve order
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -923,14 +930,17 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.B = b.B;
     F.blk.nblocks = b.nblocks;
     F.blk.perm = b.perm;
-    F.blk.slot = b.slot;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
     F.blk.ref = b.ref;
     F.blk.diag = b.diag64;
     F.blk.val = b.val64;
+    F.blk.cnt = b.cnt;
+    F.blk.ref4 = b.ref4;
+    F.blk.val4 = b.val4_64;
   }
   F.blk_scratch = blk_rhs;
+  F.blk_xr = blk_xr;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -952,14 +962,17 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.B = b.B;
     F.blk.nblocks = b.nblocks;
     F.blk.perm = b.perm;
-    F.blk.slot = b.slot;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
     F.blk.ref = b.ref;
     F.blk.diag = b.diag32;
     F.blk.val = b.val32;
+    F.blk.cnt = b.cnt;
+    F.blk.ref4 = b.ref4;
+    F.blk.val4 = b.val4_32;
   }
   F.blk_scratch = blk_rhs;
+  F.blk_xr = blk_xr;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -1748,13 +1761,19 @@ void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
     for (int pr = 0; pr < 2; pr++) {
       auto &b = C->blk[dir][pr];
       if (pr == 0) {
-        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src, b.diag64);
+        hipLaunchKernelGGL((k_gather_rdiag<double>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src,
+                           b.diag64);
         hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val64);
+        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(kNR * n)), dim3(kBlock), 0, C->st, kNR * n, b.valmap4,
+                           src, b.val4_64);
       } else {
-        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src, b.diag32);
+        hipLaunchKernelGGL((k_gather_rdiag<float>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src,
+                           b.diag32);
         hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val32);
+        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(kNR * n)), dim3(kBlock), 0, C->st, kNR * n, b.valmap4,
+                           src, b.val4_32);
       }
     }
   }
@@ -2025,18 +2044,22 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
           return d;
         };
         b.perm = up(bs.perm);
-        b.slot = up(bs.slot);
         b.slice_ptr = up(bs.slice_ptr);
         b.slice_nnz = up(bs.slice_nnz);
         b.ref = up(bs.ref);
         b.valmap = up(bs.valmap);
         b.diagmap = up(bs.diagmap);
+        b.cnt = up(bs.cnt);
+        b.ref4 = up(bs.ref4);
+        b.valmap4 = up(bs.valmap4);
         if (pr == 0) {
           b.diag64 = C->alloc<double>(n);
           b.val64 = C->alloc<double>(std::max(bs.ell, 1));
+          b.val4_64 = C->alloc<double>((size_t)kNR * n);
         } else {
           b.diag32 = C->alloc<float>(n);
           b.val32 = C->alloc<float>(std::max(bs.ell, 1));
+          b.val4_32 = C->alloc<float>((size_t)kNR * n);
         }
         C->sync();  // host vectors go out of scope
       }
@@ -2047,6 +2070,7 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     C->val32 = C->alloc<float>(nnz);
     C->ctl = C->alloc<DevCtl>(1);
     C->blk_rhs = C->alloc<double>(n);
+    C->blk_xr = C->alloc<double>(n);
     C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
     C->dflag = C->alloc<int>(4);

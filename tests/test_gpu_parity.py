@@ -253,7 +253,8 @@ def test_solve_laplace2d_closed_form(oracle_mod):
         check_pairs(A, ev, V, 1e-8)
         assert st["status"] == 0
         if prec == FP64:
-            assert st["dacg_its"] == st_o["dacg_its"]
+            # per-pair counters follow the sorted output; tied eigenvalues (lambda_2 = lambda_3) may swap
+            assert sorted(st["dacg_its"]) == sorted(st_o["dacg_its"])
             assert abs(sum(st["pcg_its"]) - sum(st_o["pcg_its"])) <= 0.1 * sum(st_o["pcg_its"])
     S.close()
 
