@@ -2,7 +2,9 @@
 // the transposed factor pattern and the level schedules of both triangular
 // solves.  Index work only; the factorisation itself runs on the device.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -122,86 +124,285 @@ void analyse(Analysis &an) {
   build_levels(n, lev, an.levLt);
 }
 
-void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs) {
+// Coordinates that never decrease along a dependency of the forward solve.  The
+// strictly lower entries (i, j) of L are classed by their index distance i - j:
+// up to three classes, cut at the two widest gaps (at least a factor 4) between
+// the frequent distances on a log scale.  Coordinate c of row i is the largest
+// number of class-c steps on a dependency path ending at i.  On a grid numbered
+// lexicographically these are the grid coordinates.
+static int dag_coords(const Analysis &an, std::vector<int> co[3]) {
+  const int n = an.n;
+  std::vector<int> dist;
+  dist.reserve(an.nnzL - n);
+  for (int i = 0; i < n; i++)
+    for (int q = an.Lrp[i]; q < an.Lrp[i + 1] - 1; q++) dist.push_back(i - an.Lci[q]);
+  std::sort(dist.begin(), dist.end());
+  std::vector<double> lg;  // log2 of the distances carrying at least 1 % of the entries
+  const size_t m = dist.size();
+  for (size_t a = 0; a < m;) {
+    size_t b = a;
+    while (b < m && dist[b] == dist[a]) b++;
+    if ((b - a) * 100 >= m) lg.push_back(std::log2((double)dist[a]));
+    a = b;
+  }
+  std::vector<std::pair<double, double>> gaps;  // (width, cut point)
+  for (size_t t = 1; t < lg.size(); t++)
+    if (lg[t] - lg[t - 1] >= 2.0) gaps.push_back({lg[t] - lg[t - 1], 0.5 * (lg[t] + lg[t - 1])});
+  std::sort(gaps.rbegin(), gaps.rend());
+  std::vector<double> cuts;
+  for (size_t t = 0; t < gaps.size() && t < 2; t++) cuts.push_back(gaps[t].second);
+  std::sort(cuts.begin(), cuts.end());
+  const int ncls = (int)cuts.size() + 1;
+  for (int c = 0; c < ncls; c++) co[c].assign(n, 0);
+  for (int i = 0; i < n; i++)
+    for (int q = an.Lrp[i]; q < an.Lrp[i + 1] - 1; q++) {
+      const int j = an.Lci[q];
+      const double l = std::log2((double)(i - j));
+      int cls = 0;
+      while (cls < (int)cuts.size() && l > cuts[cls]) cls++;
+      for (int c = 0; c < ncls; c++) co[c][i] = std::max(co[c][i], co[c][j] + (c == cls));
+    }
+  return ncls;
+}
+
+namespace {
+// Recursive bisection of the rows.  Each cut puts the rows whose value of a
+// monotone coordinate is at most a threshold first; that side holds every
+// predecessor (within the part) of its rows, so the leaves in depth-first
+// order are a topological order of the blocks.  Among the candidate
+// coordinates (the distance classes, the level, the row index) the cut with
+// the fewest dependency edges across it is taken, which keeps blocks compact
+// and a dependency path crosses few of them.
+struct Bisect {
+  const Analysis &an;
+  int cap;
+  std::vector<const std::vector<int> *> coord;
+  std::vector<int> idx, stamp_in, stamp_l, stamp_u, side;
+  int stamp = 0;
+  std::vector<int> &rows, &pstart;
+  bool ok = true;
+
+  Bisect(const Analysis &a, int c, std::vector<int> &r, std::vector<int> &p) : an(a), cap(c), rows(r), pstart(p) {}
+
+  bool fits(int a, int b) {
+    if (b - a > cap) return false;
+    ++stamp;
+    for (int t = a; t < b; t++) stamp_in[rows[t]] = stamp;
+    int imp_l = 0, imp_u = 0;
+    for (int t = a; t < b; t++) {
+      const int i = rows[t];
+      for (int q = an.Lrp[i]; q < an.Lrp[i + 1] - 1; q++) {
+        const int j = an.Lci[q];
+        if (stamp_in[j] != stamp && stamp_l[j] != stamp) {
+          stamp_l[j] = stamp;
+          imp_l++;
+        }
+      }
+      for (int q = an.Ltrp[i] + 1; q < an.Ltrp[i + 1]; q++) {
+        const int j = an.Ltci[q];
+        if (stamp_in[j] != stamp && stamp_u[j] != stamp) {
+          stamp_u[j] = stamp;
+          imp_u++;
+        }
+      }
+    }
+    return (b - a) + std::max(imp_l, imp_u) + 1 <= cap;  // + the zero slot
+  }
+  int value(int c, int i) const { return c < (int)coord.size() ? (*coord[c])[i] : i; }
+  // threshold of coordinate c splitting rows[a, b) nearest to half; false if it cannot split
+  bool threshold(int c, int a, int b, int &thr) {
+    std::vector<int> v(b - a);
+    for (int t = a; t < b; t++) v[t - a] = value(c, rows[t]);
+    const int h = (b - a) / 2;
+    std::nth_element(v.begin(), v.begin() + h, v.end());
+    const int med = v[h];
+    int below = 0, at = 0;
+    for (int x : v) {
+      below += x < med;
+      at += x == med;
+    }
+    // cut after med (below + at rows first) or before it (below rows first)
+    const int n1 = below + at, n0 = below;
+    const bool ok1 = n1 < b - a, ok0 = n0 > 0;
+    if (!ok1 && !ok0) return false;
+    if (ok1 && (!ok0 || std::abs(n1 - h) <= std::abs(n0 - h))) thr = med;
+    else thr = med - 1;
+    return true;
+  }
+  long cut_edges(int c, int a, int b, int thr) {
+    ++stamp;
+    for (int t = a; t < b; t++) {
+      stamp_in[rows[t]] = stamp;
+      side[rows[t]] = value(c, rows[t]) <= thr ? 0 : 1;
+    }
+    long cut = 0;
+    for (int t = a; t < b; t++) {
+      const int i = rows[t];
+      for (int q = an.Lrp[i]; q < an.Lrp[i + 1] - 1; q++) {
+        const int j = an.Lci[q];
+        cut += stamp_in[j] == stamp && side[j] != side[i];
+      }
+    }
+    return cut;
+  }
+  void run(int a, int b) {
+    if (!ok) return;
+    if (fits(a, b)) {
+      pstart.push_back(b);
+      return;
+    }
+    if (b - a == 1) {  // a single row that needs more than the LDS holds
+      ok = false;
+      return;
+    }
+    int best_c = -1, best_thr = 0;
+    long best_cut = -1;
+    for (int c = 0; c <= (int)coord.size(); c++) {
+      int thr;
+      if (!threshold(c, a, b, thr)) continue;
+      const long cut = cut_edges(c, a, b, thr);
+      if (best_c < 0 || cut < best_cut) {
+        best_c = c;
+        best_cut = cut;
+        best_thr = thr;
+      }
+    }
+    // the row index always splits a part of two or more rows
+    const int c = best_c, thr = best_thr;
+    auto mid = std::stable_partition(rows.begin() + a, rows.begin() + b,
+                                     [&](int i) { return value(c, i) <= thr; });
+    const int m = (int)(mid - rows.begin());
+    run(a, m);
+    run(m, b);
+  }
+};
+}  // namespace
+
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart) {
+  const int n = an.n;
+  std::vector<int> co[3];
+  const int ncls = dag_coords(an, co);
+  rows.resize(n);
+  for (int i = 0; i < n; i++) rows[i] = i;
+  pstart.assign(1, 0);
+  Bisect bi(an, cap, rows, pstart);
+  for (int c = 0; c < ncls; c++) bi.coord.push_back(&co[c]);
+  bi.coord.push_back(&an.levL.level);
+  bi.stamp_in.assign(n, 0);
+  bi.stamp_l.assign(n, 0);
+  bi.stamp_u.assign(n, 0);
+  bi.side.assign(n, 0);
+  bi.run(0, n);
+  return bi.ok;
+}
+
+void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
+                    BlockSched &bs) {
   const int n = an.n;
   const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
   const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
-  bs.n = n;
-  bs.B = B;
-  bs.nblocks = (n + B - 1) / B;
-  auto pos_of = [&](int i) { return lower ? i : n - 1 - i; };
-  auto row_at = [&](int p) { return lower ? p : n - 1 - p; };
-  // sort key: level of the row in the whole dependency graph
   const std::vector<int> &glev = lower ? an.levL.level : an.levLt.level;
-  std::vector<int> llev(n, 0);
+  const int nb = (int)pstart.size() - 1;
+  bs.n = n;
+  bs.nblocks = nb;
+  bs.bptr.assign(nb + 1, 0);
+  bs.brows.assign(nb, 0);
+  auto src_of = [&](int b) { return lower ? b : nb - 1 - b; };
+  for (int b = 0; b < nb; b++) {
+    bs.brows[b] = pstart[src_of(b) + 1] - pstart[src_of(b)];
+    bs.bptr[b + 1] = bs.bptr[b] + (bs.brows[b] + 63) / 64 * 64;
+  }
+  const int npad = bs.bptr[nb];
+  bs.npad = npad;
+  bs.perm.assign(npad, -1);
+  bs.diagmap.assign(npad, 0);
+  std::vector<int> rank(n, 0), blk(n, 0);
   bs.max_local_levels = 0;
-  for (int p = 0; p < n; p++) {
-    llev[p] = glev[row_at(p)];
-  }
-  for (int b = 0; b < bs.nblocks; b++) {
-    int lo = INT32_MAX, hi = -1;
-    for (int p = b * B; p < std::min(n, b * B + B); p++) {
-      lo = std::min(lo, llev[p]);
-      hi = std::max(hi, llev[p]);
-    }
-    bs.max_local_levels = std::max(bs.max_local_levels, hi - lo + 1);
-  }
-  // sort each block by (level, position)
-  bs.perm.assign(n, 0);
-  bs.diagmap.assign(n, 0);
-  std::vector<int> rank(n, 0), order;
-  for (int b = 0; b < bs.nblocks; b++) {
-    const int p0 = b * B, p1 = std::min(n, p0 + B);
-    order.resize(p1 - p0);
-    for (int p = p0; p < p1; p++) order[p - p0] = p;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return llev[a] < llev[c]; });
-    for (int k = p0; k < p1; k++) {
-      const int i = row_at(order[k - p0]);
+  for (int b = 0; b < nb; b++) {
+    const int s = src_of(b);
+    std::vector<int> order(rows.begin() + pstart[s], rows.begin() + pstart[s + 1]);
+    // by level, ties in solve order
+    std::sort(order.begin(), order.end(), [&](int a, int c) {
+      return glev[a] != glev[c] ? glev[a] < glev[c] : (lower ? a < c : a > c);
+    });
+    for (int t = 0; t < (int)order.size(); t++) {
+      const int i = order[t], k = bs.bptr[b] + t;
       bs.perm[k] = i;
       rank[i] = k;
+      blk[i] = b;
       bs.diagmap[k] = lower ? rp[i + 1] - 1 : rp[i];
     }
+    if (!order.empty())
+      bs.max_local_levels = std::max(bs.max_local_levels, glev[order.back()] - glev[order.front()] + 1);
   }
-  // first kNR dependencies per rank, rank-indexed
-  bs.cnt.assign(n, 0);
-  bs.ref4.assign((size_t)kNR * n, INT32_MIN);
-  bs.valmap4.assign((size_t)kNR * n, -1);
+  auto deps = [&](int i, int &e0, int &e1) {
+    e0 = lower ? rp[i] : rp[i] + 1;
+    e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
+  };
   // ELL slices of 64 ranks for the dependencies beyond kNR
-  bs.nslices = (n + 63) / 64;
+  bs.nslices = npad / 64;
   bs.slice_ptr.assign(bs.nslices + 1, 0);
   bs.slice_nnz.assign(bs.nslices, 0);
-  for (int sl = 0; sl < bs.nslices; sl++) {
-    int mx = 0;
-    for (int k = sl * 64; k < std::min(n, sl * 64 + 64); k++) {
-      const int i = bs.perm[k];
-      mx = std::max(mx, rp[i + 1] - rp[i] - 1 - kNR);
-    }
-    bs.slice_nnz[sl] = mx;
-    bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * mx;
+  bs.cnt.assign(npad, 0);
+  for (int k = 0; k < npad; k++) {
+    if (bs.perm[k] < 0) continue;
+    int e0, e1;
+    deps(bs.perm[k], e0, e1);
+    bs.cnt[k] = e1 - e0;
+    bs.slice_nnz[k / 64] = std::max(bs.slice_nnz[k / 64], e1 - e0 - kNR);
   }
+  for (int sl = 0; sl < bs.nslices; sl++) bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * bs.slice_nnz[sl];
+  // bit 30 of cnt flags the ranks of slices that hold rows longer than kNR
+  for (int k = 0; k < npad; k++)
+    if (bs.slice_nnz[k / 64] > 0) bs.cnt[k] |= kLongSlice;
   bs.ell = bs.slice_ptr[bs.nslices];
   bs.ref.assign(bs.ell, INT32_MIN);
   bs.valmap.assign(bs.ell, -1);
-  for (int k = 0; k < n; k++) {
-    const int sl = k / 64, lane = k % 64;
-    const int i = bs.perm[k];
-    const int b0 = (k / B) * B;  // first rank of the block
-    const int e0 = lower ? rp[i] : rp[i] + 1, e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
-    bs.cnt[k] = e1 - e0;
-    int e = 0;
-    for (int q = e0; q < e1; q++, e++) {
-      const int kj = rank[ci[q]];
-      const int r = (kj >= b0) ? -(kj - b0) - 1 : kj;
-      if (e < kNR) {
-        bs.ref4[(size_t)e * n + k] = r;
-        bs.valmap4[(size_t)e * n + k] = q;
-      } else {
-        const int at = bs.slice_ptr[sl] + 64 * (e - kNR) + lane;
-        bs.ref[at] = r;
-        bs.valmap[at] = q;
+  bs.ref4.assign((size_t)kNR * npad, INT32_MIN);
+  bs.valmap4.assign((size_t)kNR * npad, -1);
+  // imports in order of first use, LDS slots
+  bs.iptr.assign(nb + 1, 0);
+  bs.irow.clear();
+  bs.max_lds = 0;
+  std::vector<int> imp_blk(n, -1), imp_slot(n, 0);
+  for (int b = 0; b < nb; b++) {
+    int nimp = 0;
+    for (int k = bs.bptr[b]; k < bs.bptr[b] + bs.brows[b]; k++) {
+      int e0, e1;
+      deps(bs.perm[k], e0, e1);
+      const int sl = k / 64, lane = k % 64;
+      for (int q = e0, e = 0; q < e1; q++, e++) {
+        const int j = ci[q];
+        int slot;
+        if (blk[j] == b) {
+          slot = rank[j] - bs.bptr[b];
+        } else {
+          if (imp_blk[j] != b) {
+            imp_blk[j] = b;
+            imp_slot[j] = nimp++;
+            bs.irow.push_back(j);
+          }
+          slot = bs.brows[b] + imp_slot[j];
+        }
+        if (e < kNR) {
+          bs.ref4[(size_t)e * npad + k] = -slot - 1;
+          bs.valmap4[(size_t)e * npad + k] = q;
+        } else {
+          const int at = bs.slice_ptr[sl] + 64 * (e - kNR) + lane;
+          bs.ref[at] = -slot - 1;
+          bs.valmap[at] = q;
+        }
       }
     }
+    bs.iptr[b + 1] = bs.iptr[b] + nimp;
+    // unused register-cached entries read the block's zero slot (value 0, weight 0)
+    const int zero = -(bs.brows[b] + nimp) - 1;
+    for (int k = bs.bptr[b]; k < bs.bptr[b + 1]; k++)
+      for (int q = 0; q < kNR; q++)
+        if (bs.ref4[(size_t)q * npad + k] == INT32_MIN) bs.ref4[(size_t)q * npad + k] = zero;
+    bs.max_lds = std::max(bs.max_lds, bs.brows[b] + nimp + 1);
   }
+  bs.nimp = bs.iptr[nb];
 }
 
 }  // namespace bnx

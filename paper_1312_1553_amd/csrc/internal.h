@@ -58,27 +58,40 @@ struct Levels {
   int max_rows = 0;
 };
 
-// Block schedule of one triangular solve ("LDS-staged" sync-free solve).
-// Rows are taken in solve order (position pos = i for L, n-1-i for L^T, so every
-// dependency has a smaller position), cut into blocks of B consecutive
-// positions, and each block is sorted by the rows' level in the whole
-// dependency graph, so that all blocks advance through the levels together and
-// the rows a block needs from earlier blocks are produced early.  A row's rank
-// k is its index in that order (block b holds ranks b*B .. b*B+B-1).
-// The first kNR dependencies of rank k are at [q * n + k] (q < kNR) of ref4 /
-// valmap4; further ones of long rows are stored as 64-row ELL slices: entry
-// e >= kNR of lane l of slice s is at slice_ptr[s] + 64 (e - kNR) + l.
-// ref >= 0 is an external dependency (its global rank), ref < 0 an in-block
-// one (local rank -ref-1); unused entries have ref = INT_MIN.
+// Block schedule of one triangular solve (LDS-staged sync-free solve).
+// The rows are partitioned into blocks (partition_rows); the block order is a
+// topological order of the solve's dependency graph, and inside a block the
+// rows are sorted by their level in the whole graph.  A row's rank k is its
+// index in that order: block b occupies ranks bptr[b] .. bptr[b]+brows[b]-1,
+// padded up to a multiple of 64 (padding ranks: cnt 0, perm -1).
+// A block keeps every value it reads in LDS: its own rows at their local rank,
+// and the rows it needs from earlier blocks ("imports": irow[iptr[b] ..
+// iptr[b+1]-1], original row ids in order of first use) at brows[b] + import
+// index, followed by one slot that holds 0.  The first kNR dependencies of
+// rank k are at [q * npad + k] of ref4 / valmap4 (q < kNR), encoded as
+// -(LDS slot)-1; unused ones point at the zero slot with valmap -1 (weight 0),
+// so a row always reads kNR values.  Further dependencies of long rows are
+// stored as 64-rank ELL slices: entry e >= kNR of lane l of slice s is at
+// slice_ptr[s] + 64 (e - kNR) + l (ELL padding: ref INT_MIN, valmap -1).
 constexpr int kNR = 4;
+constexpr int kLongSlice = 1 << 30;  // flag in cnt: the rank's slice has rows longer than kNR
+// LDS values per block (rows + imports + the zero slot): 159 KiB of the 160 KiB of a CU.
+constexpr int kLdsCap64 = 20352;
+constexpr int kLdsCap32 = 40704;
+constexpr int kBlkTarget = 3584;  // default LDS values per block of the partition
+
 struct BlockSched {
-  int n = 0, B = 0, nblocks = 0, nslices = 0, ell = 0;
-  int max_local_levels = 0;
-  std::vector<int> perm;       // n: original row of rank k
-  std::vector<int> diagmap;    // n: factor value index of the diagonal of row perm[k]
-  std::vector<int> cnt;        // n: number of dependencies of rank k
-  std::vector<int> ref4;       // kNR * n
-  std::vector<int> valmap4;    // kNR * n, -1 where unused
+  int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;
+  int max_local_levels = 0, max_lds = 0;
+  std::vector<int> bptr;       // nblocks+1: first (padded) rank of each block
+  std::vector<int> brows;      // nblocks: rows of each block
+  std::vector<int> iptr;       // nblocks+1: imports of each block
+  std::vector<int> irow;       // imported rows (original ids), in order of first use
+  std::vector<int> perm;       // npad: original row of rank k (-1: padding)
+  std::vector<int> diagmap;    // npad: factor value index of the diagonal of row perm[k]
+  std::vector<int> cnt;        // npad: number of dependencies of rank k (| kLongSlice)
+  std::vector<int> ref4;       // kNR * npad
+  std::vector<int> valmap4;    // kNR * npad, -1 where unused
   std::vector<int> slice_ptr;  // nslices+1
   std::vector<int> slice_nnz;  // nslices: entries beyond kNR
   std::vector<int> ref;        // ell entries
@@ -98,13 +111,20 @@ struct Analysis {
 std::string validate_csr(int n, int nnz, const int *rp, const int *ci);
 // Build L / L^T patterns and level schedules.
 void analyse(Analysis &an);
+// Partition of the rows into blocks of at most cap LDS values each (the block's
+// rows plus the distinct rows it reads from other blocks, in either solve
+// direction).  Blocks are rows[pstart[b] .. pstart[b+1]-1], listed in a
+// topological order of the forward graph.  Returns false when a single row
+// does not fit.
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart);
 // Block schedule of the forward (lower = true: rows of L, diag last) or backward
-// (rows of L^T, diag first) solve with B rows per block.
-void block_schedule(const Analysis &an, bool lower, int B, BlockSched &bs);
+// (rows of L^T, diag first) solve over a partition from partition_rows (the
+// backward solve takes its blocks in reverse order).
+void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
+                    BlockSched &bs);
 
 // ----------------------------------------------------------------- launchers
 int spmv_group(double mean_nnz);
-int block_rows_for(int elem_bytes);
 
 template <typename T>
 struct Mat {
@@ -121,7 +141,8 @@ struct Mat {
 // Device copy of a BlockSched with values of precision T.
 template <typename T>
 struct DevBlk {
-  int n = 0, B = 0, nblocks = 0;
+  int n = 0, npad = 0, nblocks = 0;
+  const int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *irow = nullptr;
   const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
   const int *cnt = nullptr, *ref4 = nullptr;
   const T *diag = nullptr, *val = nullptr, *val4 = nullptr;  // diag holds reciprocals
@@ -130,8 +151,7 @@ struct DevBlk {
 template <typename T>
 struct Tri {
   DevBlk<T> blk;
-  void *blk_scratch = nullptr;  // n values: right-hand side in solve order
-  void *blk_xr = nullptr;       // n values: solution in solve order (polled by later blocks)
+  void *blk_scratch = nullptr;  // npad values: right-hand side in rank order
   int n = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;

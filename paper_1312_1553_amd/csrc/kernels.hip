@@ -300,16 +300,20 @@ __global__ void k_sentinel(size_t n, T *x, int *counter, const int *gate) {
 }
 
 constexpr int kSpinLimit = 1 << 20;
-// Block solve polling: LDS polling rounds between examinations of the external
-// polls, and the s_sleep issued after a polling round without progress.
-#ifndef BNX_TRSV_ILIM
-#define BNX_TRSV_ILIM 2
-#endif
+// Block solve: s_sleep of a compute wave after a polling round without progress
+// (0: none), s_wakeup of the workgroup after a round that stored values, compute
+// and importer waves per workgroup (the rest publish), s_sleep of a publisher poll.
 #ifndef BNX_TRSV_SLEEP
 #define BNX_TRSV_SLEEP 0
 #endif
 #ifndef BNX_TRSV_WC
-#define BNX_TRSV_WC 12
+#define BNX_TRSV_WC 10
+#endif
+#ifndef BNX_TRSV_WAKE
+#define BNX_TRSV_WAKE 0
+#endif
+#ifndef BNX_TRSV_WI
+#define BNX_TRSV_WI 2
 #endif
 #ifndef BNX_TRSV_PUBSLEEP
 #define BNX_TRSV_PUBSLEEP 1
@@ -378,26 +382,27 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
   }
 }
 
-// LDS-staged sync-free solve: one 1024-thread workgroup per block of B rows
-// (taken in block order from a ticket counter).  The block's solution lives in
-// LDS; in-block dependencies are read from LDS, external ones (earlier blocks)
-// from the global solution, both polled until they leave the sentinel state.
-// Each wave walks its 64-row slices of the block in order (rows sorted by local
-// level), so a lane only waits on rows of lower rank, which finish first.
-// Right-hand side in solve order and sentinel fill of the rank-ordered solution:
-//   bp[k] = b[perm[k]] - sum_t coef[t] R_t[perm[k]],  xr[k] = sentinel,  counter = 0.
+// First launch of the LDS-staged solve.  part & 1: right-hand side in rank
+// order, bp[k] = b_i - sum_t coef[t] R_t[i] for i = perm[k] (0 on padding ranks);
+// part & 2: sentinel fill of the solution x (every value a block imports is
+// polled in x until it leaves the sentinel state) and reset of the ticket counter.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsv_prep(int n, const int *__restrict__ perm, const T *__restrict__ b,
-                                                      int kfuse, VList<T> R, const double *coef, T *bp, T *xr,
-                                                      int *counter, const int *gate) {
+__global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int n, int npad, const int *__restrict__ perm,
+                                                      const T *__restrict__ b, int kfuse, VList<T> R,
+                                                      const double *coef, T *bp, T *x, int *counter,
+                                                      const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
-  U *xu = reinterpret_cast<U *>(xr);
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < n; k += gridDim.x * kBlock) {
-    bp[k] = rhs_value(perm[k], b, kfuse, R, coef);
-    xu[k] = Sentinel<T>::bits;
+  if (part & 1)
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < npad; k += gridDim.x * kBlock) {
+      const int i = perm[k];
+      bp[k] = i >= 0 ? rhs_value(i, b, kfuse, R, coef) : T(0);
+    }
+  if (part & 2) {
+    U *xu = reinterpret_cast<U *>(x);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
 template <typename T, int NR>
@@ -408,103 +413,198 @@ struct RowPre {
   T vv[NR];
 };
 
-// Row data of rank base+lane (all loads rank-indexed and independent of each other).
+// Row data of rank k: rank-indexed loads only, none conditional (the caller
+// passes a valid rank for lanes without a row), so the compiler can count the
+// loads in flight exactly and wait only for the ones it needs.
 template <typename T, int NR>
-__device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int base, int k1, int lane,
-                                          RowPre<T, NR> &R) {
-  const int k = base + lane;
-  const bool ok = k < k1;
-  const int n = F.n;
-  R.cnt = ok ? F.cnt[k] : 0;
-  R.d = ok ? F.diag[k] : T(1);  // reciprocal of the diagonal
-  R.s = ok ? bp[k] : T(0);
+__device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k, RowPre<T, NR> &P) {
+  const int np = F.npad;
+  P.cnt = F.cnt[k];
+  P.d = F.diag[k];  // reciprocal of the diagonal
+  P.s = bp[k];
 #pragma unroll
   for (int q = 0; q < NR; q++) {
-    R.rr[q] = ok ? F.ref4[(size_t)q * n + k] : INT32_MIN;
-    R.vv[q] = ok ? F.val4[(size_t)q * n + k] : T(0);
+    P.rr[q] = F.ref4[(size_t)q * np + k];
+    P.vv[q] = F.val4[(size_t)q * np + k];
   }
 }
 
-// LDS-staged sync-free solve.  One 1024-thread workgroup per block of B ranks
-// (blocks taken in order from a ticket counter); the block's solution lives in
-// LDS, indexed by local rank.
-//  * 12 compute waves walk the block's 64-row slices in order (wave w takes
-//    slices w, w+12, ...).  A lane resolves its row's dependencies from LDS
-//    (in-block) or by polling the rank-ordered global solution xr (earlier
-//    blocks), and writes its result to LDS only, so compute waves never wait
-//    on their own stores.
-//  * 4 publisher waves copy finished LDS values to xr (coalesced, for later
-//    blocks) and to the output x (original order).
-// Every dependency has a lower rank, so the lowest unfinished row can always
-// proceed.  Waits are bounded: on overflow the value becomes NaN and *err is set.
-template <typename T, int B>
-__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xr, int *counter,
+// LDS-staged sync-free solve.  One 1024-thread workgroup per block of the
+// schedule (blocks taken in order from a ticket counter; the order is
+// topological, so a block only waits on blocks that started before it).  Every
+// value a block reads lives in its LDS: its own rows at their local rank and
+// the values it imports from earlier blocks behind them.
+//  * WC compute waves walk the block's 64-row slices in order (wave w takes
+//    slices w, w+WC, ...).  A lane polls its row's dependencies in LDS, and
+//    writes the result to LDS only, so compute waves never touch global memory
+//    for the dependency chain.
+//  * WP publisher waves copy finished values to the solution x in global
+//    memory (device-scope stores: other blocks import from there).
+//  * WI importer waves poll x for the block's imports, in order of first use,
+//    and copy them into LDS.
+// Every dependency of a row has a lower rank or is an import, so the lowest
+// unfinished row can always proceed.  Waits are bounded: on overflow the value
+// becomes NaN and *err is set.
+template <typename T, int CAP>
+__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, int *counter,
                                                     int *err, const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
   constexpr int NR = kNR;  // dependencies cached in registers per row
-  constexpr int WC = BNX_TRSV_WC;  // compute waves
-  constexpr int WP = 16 - WC;
-  __shared__ U xs[B];
+  constexpr int WC = BNX_TRSV_WC, WI = BNX_TRSV_WI;
+  constexpr int WP = 16 - WC - WI;
+  static_assert(WP >= 1 && WI >= 1, "wave roles");
+  __shared__ U xs[CAP];
   __shared__ int blk_s;
   if (threadIdx.x == 0) blk_s = atomicAdd(counter, 1);
-  for (int i = threadIdx.x; i < B; i += 1024) xs[i] = Sentinel<T>::bits;
   __syncthreads();
   const int blk = blk_s;
   if (blk >= F.nblocks) return;
-  U *xru = reinterpret_cast<U *>(xr);
+  const int k0 = F.bptr[blk], nrow = F.brows[blk];
+  const int i0 = F.iptr[blk], nimp = F.iptr[blk + 1] - i0;
+  for (int i = threadIdx.x; i <= nrow + nimp; i += 1024) xs[i] = i < nrow + nimp ? Sentinel<T>::bits : U(0);
+  __syncthreads();
   U *xu = reinterpret_cast<U *>(x);
-  const int n = F.n;
-  const int k0 = blk * B, k1 = (k0 + B < n) ? k0 + B : n;
-  const int nsl = (k1 - k0 + 63) >> 6;
+  const int nsl = (nrow + 63) >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
-  if (wave >= WC) {  // publisher
-    for (int sl = wave - WC; sl < nsl; sl += WP) {
-      const int t = (sl << 6) + lane;
-      const int k = k0 + t;
-      if (k < k1) {
-        const int row = F.perm[k];
-        U u;
-        int spins = 0;
-        while ((u = __hip_atomic_load(&xs[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == Sentinel<T>::bits) {
-          if (++spins > kSpinLimit) {
-            u = to_bits<T>(T(__builtin_nan("")));
+  if (wave >= WC + WP) {  // importer: two imports per lane in flight, the next two rows prefetched
+    const int step = WI * 128;
+    int base = (wave - WC - WP) * 128;
+    int r0 = base + lane < nimp ? F.irow[i0 + base + lane] : -1;
+    int r1 = base + 64 + lane < nimp ? F.irow[i0 + base + 64 + lane] : -1;
+    for (; base < nimp; base += step) {
+      const int e0 = base + lane, e1 = base + 64 + lane;
+      const int n0 = base + step + lane < nimp ? F.irow[i0 + base + step + lane] : -1;
+      const int n1 = base + step + 64 + lane < nimp ? F.irow[i0 + base + step + 64 + lane] : -1;
+      bool p0 = r0 >= 0, p1 = r1 >= 0;
+      int spins = 0;
+      while (__builtin_amdgcn_ballot_w64(p0 || p1) != 0ull) {
+        if (p0 || p1) {
+          U u0 = p0 ? __hip_atomic_load(&xu[r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
+          U u1 = p1 ? __hip_atomic_load(&xu[r1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
+          if (++spins > kSpinLimit) {  // bounded wait: pending imports become NaN
+            const U nan = to_bits<T>(T(__builtin_nan("")));
+            if (u0 == Sentinel<T>::bits) u0 = nan;
+            if (u1 == Sentinel<T>::bits) u1 = nan;
             atomicOr(err, 1);
-            break;
           }
-          if (BNX_TRSV_PUBSLEEP > 0) __builtin_amdgcn_s_sleep(BNX_TRSV_PUBSLEEP);
+          if (p0 && u0 != Sentinel<T>::bits) {
+            __hip_atomic_store(&xs[nrow + e0], u0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            p0 = false;
+          }
+          if (p1 && u1 != Sentinel<T>::bits) {
+            __hip_atomic_store(&xs[nrow + e1], u1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            p1 = false;
+          }
         }
-        __hip_atomic_store(&xru[k], u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        xu[row] = u;
+        if (BNX_TRSV_WAKE) __asm__ volatile("s_wakeup");
       }
+      r0 = n0;
+      r1 = n1;
     }
     return;
   }
 
-  // two rounds of row data in flight ahead of the current one
-  RowPre<T, NR> cur, nx1, nx2;
-  if (wave < nsl) row_fetch<T, NR>(F, bp, k0 + (wave << 6), k1, lane, nx1);
-  if (wave + WC < nsl) row_fetch<T, NR>(F, bp, k0 + ((wave + WC) << 6), k1, lane, nx2);
-  for (int sl = wave; sl < nsl; sl += WC) {
-    const int base = k0 + (sl << 6);
-    cur = nx1;
-    nx1 = nx2;
-    if (sl + 2 * WC < nsl) row_fetch<T, NR>(F, bp, k0 + ((sl + 2 * WC) << 6), k1, lane, nx2);
-    const int t = base - k0 + lane;
-    bool fin = base + lane >= k1;
-    const int nown = cur.cnt < NR ? cur.cnt : NR;
-    const int nlong = cur.cnt;  // entries beyond NR come from the ELL slices
-    const int gsl = base >> 6;
-    const int esp = nlong > NR ? F.slice_ptr[gsl] + lane : 0;
-    unsigned need_l = 0, need_g = 0;
+  if (wave >= WC) {  // publisher: PG slices at a time, each value goes out as soon as it is in LDS
+    constexpr int PG = 4;
+    const int p = wave - WC;
+    // own slices are p, p + WP, p + 2 WP, ...; group j holds own slices j*PG .. j*PG+PG-1
+    auto group_rows = [&](int j, int (&r)[PG]) {
 #pragma unroll
-    for (int q = 0; q < NR; q++) {
-      if (q < nown) {
-        if (cur.rr[q] < 0) need_l |= 1u << q;
-        else need_g |= 1u << q;
+      for (int g = 0; g < PG; g++) {
+        const int sl = p + WP * (j * PG + g), t = (sl << 6) + lane;
+        r[g] = (sl < nsl && t < nrow) ? F.perm[k0 + t] : -1;
       }
+    };
+    int cur[PG], nxt[PG];
+    group_rows(0, cur);
+    for (int j = 0; p + WP * j * PG < nsl; j++) {
+      group_rows(j + 1, nxt);
+      unsigned pend = 0;
+#pragma unroll
+      for (int g = 0; g < PG; g++) pend |= (cur[g] >= 0 ? 1u : 0u) << g;
+      int spins = 0;
+      while (__builtin_amdgcn_ballot_w64(pend != 0u) != 0ull) {
+        if (pend) {
+          U u[PG];
+#pragma unroll
+          for (int g = 0; g < PG; g++) {
+            const int t = ((p + WP * (j * PG + g)) << 6) + lane;
+            u[g] = (pend >> g & 1u) ? __hip_atomic_load(&xs[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                                    : Sentinel<T>::bits;
+          }
+          const bool over = ++spins > kSpinLimit;
+          if (over) atomicOr(err, 1);
+#pragma unroll
+          for (int g = 0; g < PG; g++)
+            if (pend >> g & 1u) {
+              U v = u[g];
+              if (v == Sentinel<T>::bits && over) v = to_bits<T>(T(__builtin_nan("")));
+              if (v != Sentinel<T>::bits) {
+                __hip_atomic_store(&xu[cur[g]], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pend &= ~(1u << g);
+              }
+            }
+        }
+        if (BNX_TRSV_PUBSLEEP > 0) __builtin_amdgcn_s_sleep(BNX_TRSV_PUBSLEEP);
+      }
+#pragma unroll
+      for (int g = 0; g < PG; g++) cur[g] = nxt[g];
     }
+    return;
+  }
+
+  // compute: row data of the next three slices in flight while one is solved;
+  // the four buffers rotate statically (no register copies, which would wait on
+  // the loads in flight)
+  auto fetch = [&](int sl, RowPre<T, NR> &P) {
+    const int t = (sl << 6) + lane;
+    row_fetch<T, NR>(F, bp, (sl < nsl && t < nrow) ? k0 + t : k0, P);
+  };
+  // The polling loop runs until no lane of the wave is pending (a ballot), so a
+  // row's store sits inside the iteration in which it finishes: code after a
+  // divergent loop exit would only run once the whole wave has left the loop,
+  // and rows of one slice may depend on each other.
+  auto solve_slice = [&](const RowPre<T, NR> &cur, int sl) {
+    const int t = (sl << 6) + lane;
+    bool fin = t >= nrow;
+    const int gsl = (k0 >> 6) + sl;
+    // lane 0 always holds a row of the slice; its flag tells whether any row is long
+    if ((__builtin_amdgcn_readfirstlane(cur.cnt) & kLongSlice) == 0) {
+      // every row of the slice has at most NR dependencies (unused ones read the
+      // zero slot): read all NR values each round, finish when none is a sentinel
+      int spins = 0;
+      while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
+        if (!fin) {
+          U u[NR];
+#pragma unroll
+          for (int q = 0; q < NR; q++)
+            u[q] = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          bool ok = true;
+#pragma unroll
+          for (int q = 0; q < NR; q++) ok = ok && u[q] != Sentinel<T>::bits;
+          if (ok) {
+            T acc = cur.s;
+#pragma unroll
+            for (int q = 0; q < NR; q++) acc -= cur.vv[q] * from_bits<T>(u[q]);
+            __hip_atomic_store(&xs[t], to_bits<T>(acc * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            fin = true;
+          }
+        }
+        if (++spins > kSpinLimit && !fin) {
+          __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+          atomicOr(err, 1);
+          fin = true;
+        }
+      }
+      return;
+    }
+    const int nlong = cur.cnt & ~kLongSlice;  // entries beyond NR come from the ELL slices
+    const int nown = nlong < NR ? nlong : NR;
+    const int esp = F.slice_ptr[gsl] + lane;
+    const unsigned need = (1u << nown) - 1u;
     T xv[NR];
 #pragma unroll
     for (int q = 0; q < NR; q++) xv[q] = T(0);
@@ -512,107 +612,83 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     bool cached_done = false;
     T s = cur.s;
     int e = NR, spins = 0;
-    while (!fin) {
-      // 1) polls of external dependencies, examined after the LDS phase (skipped by the
-      //    whole wave when no lane has one pending, so no memory wait is needed then)
-      const bool gpend = (need_g & ~seen) != 0u;
-      const bool anyg = __builtin_amdgcn_ballot_w64(gpend) != 0ull;
-      U gv[NR];
-      if (anyg) {
+    while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
+      const unsigned seen0 = seen;
+      const bool fin0 = fin;
+      if (!fin) {
+        const unsigned pend = need & ~seen;
+        if (pend) {
+          U lv[NR];
 #pragma unroll
-        for (int q = 0; q < NR; q++)
-          gv[q] = ((need_g & ~seen) >> q & 1u)
-                      ? __hip_atomic_load(&xru[cur.rr[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                      : Sentinel<T>::bits;
-      }
-      // 2) LDS phase; a row whose dependencies have all arrived finishes here
-      for (int it = 0; it < BNX_TRSV_ILIM && !fin && (need_l & ~seen); it++, spins++) {
-        const unsigned pend = need_l & ~seen;
-        U lv[NR];
+          for (int q = 0; q < NR; q++)  // all polls issued before any result is examined
+            lv[q] = (pend >> q & 1u)
+                        ? __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                        : Sentinel<T>::bits;
 #pragma unroll
-        for (int q = 0; q < NR; q++)  // all LDS polls issued before any result is examined
-          lv[q] = (pend >> q & 1u)
-                      ? __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                      : Sentinel<T>::bits;
+          for (int q = 0; q < NR; q++)
+            if ((pend >> q & 1u) && lv[q] != Sentinel<T>::bits) {
+              xv[q] = from_bits<T>(lv[q]);
+              seen |= 1u << q;
+            }
+        }
+        if (seen == need) {
+          if (!cached_done) {
 #pragma unroll
-        for (int q = 0; q < NR; q++)
-          if ((pend >> q & 1u) && lv[q] != Sentinel<T>::bits) {
-            xv[q] = from_bits<T>(lv[q]);
-            seen |= 1u << q;
+            for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
+            cached_done = true;
           }
-        if (BNX_TRSV_SLEEP > 0 && (need_l & ~seen) == pend) __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
-        if (seen == (need_l | need_g) && nlong <= NR) {
-#pragma unroll
-          for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
-          __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          // rows longer than the register cache: the remaining entries in order
+          while (e < nlong) {
+            const int at = esp + 64 * (e - NR);
+            const U u = __hip_atomic_load(&xs[-F.ref[at] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (u == Sentinel<T>::bits) break;
+            s -= F.val[at] * from_bits<T>(u);
+            e++;
+          }
+          if (e >= nlong) {
+            __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            fin = true;
+          }
+        }
+        if (!fin && ++spins > kSpinLimit) {
+          __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+          atomicOr(err, 1);
           fin = true;
         }
       }
-      if (fin) break;
-      // 3) results of the external polls
-      if (anyg) {
-#pragma unroll
-        for (int q = 0; q < NR; q++)
-          if (((need_g & ~seen) >> q & 1u) && gv[q] != Sentinel<T>::bits) {
-            xv[q] = from_bits<T>(gv[q]);
-            seen |= 1u << q;
-          }
-      }
-      if (seen == (need_l | need_g)) {
-        if (!cached_done) {
-#pragma unroll
-          for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
-          cached_done = true;
-        }
-        // rows longer than the register cache: the remaining entries in order
-        bool blocked = false;
-        while (e < nlong) {
-          const int at = esp + 64 * (e - NR);
-          const int r = F.ref[at];
-          const U u = r < 0 ? __hip_atomic_load(&xs[-r - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                            : __hip_atomic_load(&xru[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (u == Sentinel<T>::bits) {
-            blocked = true;
-            break;
-          }
-          s -= F.val[at] * from_bits<T>(u);
-          e++;
-        }
-        if (!blocked) {
-          __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          fin = true;
-          break;
-        }
-      }
-      if (++spins > kSpinLimit) {
-        __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        atomicOr(err, 1);
-        fin = true;
-      } else if (!(need_l & ~seen)) {
-        __builtin_amdgcn_s_sleep(1);  // only external dependencies left
+      // a round without progress yields the SIMD to the other waves; a round that
+      // stored values wakes the waves of the workgroup that sleep
+      const bool moved = fin != fin0 || seen != seen0;
+      if (__builtin_amdgcn_ballot_w64(moved) == 0ull) {
+        if (BNX_TRSV_SLEEP > 0) __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
+      } else if (BNX_TRSV_WAKE && __builtin_amdgcn_ballot_w64(fin != fin0) != 0ull) {
+        __asm__ volatile("s_wakeup");
       }
     }
+  };
+  RowPre<T, NR> A, B, C, D;
+  fetch(wave, A);
+  fetch(wave + WC, B);
+  fetch(wave + 2 * WC, C);
+  for (int sl = wave; sl < nsl; sl += 4 * WC) {
+    fetch(sl + 3 * WC, D);
+    solve_slice(A, sl);
+    if (sl + WC >= nsl) break;
+    fetch(sl + 4 * WC, A);
+    solve_slice(B, sl + WC);
+    if (sl + 2 * WC >= nsl) break;
+    fetch(sl + 5 * WC, B);
+    solve_slice(C, sl + 2 * WC);
+    if (sl + 3 * WC >= nsl) break;
+    fetch(sl + 6 * WC, C);
+    solve_slice(D, sl + 3 * WC);
   }
 }
 
-template <typename T>
-constexpr int blk_rows() {
-  return (128 * 1024) / (int)sizeof(T);
-}
-// Rows per block: the largest block whose solution fits 128 KiB of LDS, unless
-// overridden (BNX_BLK_ROWS, a power of two from 1024 up to that size).
-int block_rows_for(int elem_bytes) {
-  const int mx = elem_bytes == 8 ? blk_rows<double>() : blk_rows<float>();
-  if (const char *e = getenv("BNX_BLK_ROWS")) {
-    const int v = atoi(e);
-    if (v >= 1024 && v <= mx && (v & (v - 1)) == 0) return v;
-  }
-  return mx;
-}
-
-template <typename T, int B>
-static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, T *xr, const int *gate) {
-  hipLaunchKernelGGL((k_trsv_blk<T, B>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, xr, L.counter,
+template <typename T, int CAP>
+static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
+  hipLaunchKernelGGL((k_trsv_blk<T, CAP>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, L.counter,
                      &L.ctl->err, gate);
 }
 
@@ -623,18 +699,16 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
     const bool prof0 = L.prof && L.prof->on;
     hipEvent_t ev0 = nullptr;
     T *bp = reinterpret_cast<T *>(F.blk_scratch);
-    T *xr = reinterpret_cast<T *>(F.blk_xr);
-    hipLaunchKernelGGL((k_trsv_prep<T>), dim3(grid_for(F.n, kNBMax)), dim3(kBlock), 0, L.st, F.n, F.blk.perm, b, kfuse,
-                       R, coef, bp, xr, L.counter, gate);
+    const int nb = grid_for((size_t)F.blk.npad, kNBMax);
+    // a right-hand side that aliases the solution is read completely before the sentinel fill
+    const bool alias = (const void *)b == (const void *)x;
+    const int parts[2] = {alias ? 1 : 3, 2};
+    for (int q = 0; q < (alias ? 2 : 1); q++)
+      hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, parts[q], F.n, F.blk.npad, F.blk.perm,
+                         b, kfuse, R, coef, bp, x, L.counter, gate);
     if (prof0) L.prof->begin(L.st, &ev0);
-    switch (F.blk.B) {
-      case 1024: launch_blk<T, 1024>(L, F, bp, x, xr, gate); break;
-      case 2048: launch_blk<T, 2048>(L, F, bp, x, xr, gate); break;
-      case 4096: launch_blk<T, 4096>(L, F, bp, x, xr, gate); break;
-      case 8192: launch_blk<T, 8192>(L, F, bp, x, xr, gate); break;
-      case 16384: launch_blk<T, 16384>(L, F, bp, x, xr, gate); break;
-      default: launch_blk<T, blk_rows<T>()>(L, F, bp, x, xr, gate); break;
-    }
+    if constexpr (sizeof(T) == 8) launch_blk<T, kLdsCap64>(L, F, bp, x, gate);
+    else launch_blk<T, kLdsCap32>(L, F, bp, x, gate);
     if (prof0) L.prof->end(L.st, (F.lower ? 2 : 4) + (sizeof(T) == 8 ? 0 : 1), ev0);
     return;
   }

@@ -814,14 +814,14 @@ struct bnx_ctx {
   float *Lv32 = nullptr, *Ltv32 = nullptr;
   // block schedules of the LDS-staged solve: [0] forward (L), [1] backward (L^T); per precision
   struct BlkDev {
-    int n = 0, B = 0, nblocks = 0, ell = 0;
+    int n = 0, npad = 0, nblocks = 0, ell = 0;
+    int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *irow = nullptr;
     int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
     int *valmap = nullptr, *diagmap = nullptr, *cnt = nullptr, *ref4 = nullptr, *valmap4 = nullptr;
     double *diag64 = nullptr, *val64 = nullptr, *val4_64 = nullptr;
     float *diag32 = nullptr, *val32 = nullptr, *val4_32 = nullptr;
-  } blk[2][2];  // [direction][0 = fp64 block size, 1 = fp32 block size]
-  double *blk_rhs = nullptr;  // n doubles: right-hand side of a block solve in solve order
-  double *blk_xr = nullptr;   // n doubles: its solution in solve order
+  } blk[2][2];  // [direction][0 = fp64 LDS capacity, 1 = fp32 LDS capacity]
+  double *blk_rhs = nullptr;  // right-hand side of a block solve in rank order (largest npad)
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -927,8 +927,12 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   {
     const BlkDev &b = blk[lower ? 0 : 1][0];
     F.blk.n = b.n;
-    F.blk.B = b.B;
+    F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
+    F.blk.bptr = b.bptr;
+    F.blk.brows = b.brows;
+    F.blk.iptr = b.iptr;
+    F.blk.irow = b.irow;
     F.blk.perm = b.perm;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
@@ -940,7 +944,6 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.val4 = b.val4_64;
   }
   F.blk_scratch = blk_rhs;
-  F.blk_xr = blk_xr;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -959,8 +962,12 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
   {
     const BlkDev &b = blk[lower ? 0 : 1][1];
     F.blk.n = b.n;
-    F.blk.B = b.B;
+    F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
+    F.blk.bptr = b.bptr;
+    F.blk.brows = b.brows;
+    F.blk.iptr = b.iptr;
+    F.blk.irow = b.irow;
     F.blk.perm = b.perm;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
@@ -972,7 +979,6 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.val4 = b.val4_32;
   }
   F.blk_scratch = blk_rhs;
-  F.blk_xr = blk_xr;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -1760,20 +1766,22 @@ void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
     const double *src = dir == 0 ? C->Lv : C->Ltv;
     for (int pr = 0; pr < 2; pr++) {
       auto &b = C->blk[dir][pr];
+      if (b.nblocks == 0) continue;
+      const int np = b.npad;
       if (pr == 0) {
-        hipLaunchKernelGGL((k_gather_rdiag<double>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src,
+        hipLaunchKernelGGL((k_gather_rdiag<double>), dim3(gridn(np)), dim3(kBlock), 0, C->st, np, b.diagmap, src,
                            b.diag64);
         hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val64);
-        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(kNR * n)), dim3(kBlock), 0, C->st, kNR * n, b.valmap4,
-                           src, b.val4_64);
+        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(kNR * np)), dim3(kBlock), 0, C->st, kNR * np,
+                           b.valmap4, src, b.val4_64);
       } else {
-        hipLaunchKernelGGL((k_gather_rdiag<float>), dim3(gridn(n)), dim3(kBlock), 0, C->st, n, b.diagmap, src,
+        hipLaunchKernelGGL((k_gather_rdiag<float>), dim3(gridn(np)), dim3(kBlock), 0, C->st, np, b.diagmap, src,
                            b.diag32);
         hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val32);
-        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(kNR * n)), dim3(kBlock), 0, C->st, kNR * n, b.valmap4,
-                           src, b.val4_32);
+        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(kNR * np)), dim3(kBlock), 0, C->st, kNR * np,
+                           b.valmap4, src, b.val4_32);
       }
     }
   }
@@ -2029,20 +2037,35 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     if (!v.empty()) throw ApiError{BNX_E_ARG, v};
     analyse(C->an);
     C->group = spmv_group((double)nnz / (double)n);
-    for (int dir = 0; dir < 2; dir++)
-      for (int pr = 0; pr < 2; pr++) {
+    for (int pr = 0; pr < 2; pr++) {
+      std::vector<int> prow, pstart;
+      // Block size target: smaller blocks shorten the in-block chain latency per
+      // level, larger ones cross fewer block boundaries; measured best near 3.5k
+      // rows on the 7-point 100^3 grid in both precisions.
+      int cap = kBlkTarget;
+      if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
+        cap = atoi(e);
+      cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
+      if (!partition_rows(C->an, cap, prow, pstart)) continue;  // no block schedule
+      for (int dir = 0; dir < 2; dir++) {
         BlockSched bs;
-        block_schedule(C->an, dir == 0, block_rows_for(pr == 0 ? 8 : 4), bs);
+        block_schedule(C->an, dir == 0, prow, pstart, bs);
+        if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
         auto &b = C->blk[dir][pr];
         b.n = bs.n;
-        b.B = bs.B;
+        b.npad = bs.npad;
         b.nblocks = bs.nblocks;
         b.ell = bs.ell;
         auto up = [&](const std::vector<int> &v) {
-          int *d = C->alloc<int>(v.size());
-          HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
+          int *d = C->alloc<int>(std::max<size_t>(v.size(), 1));
+          if (!v.empty())
+            HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
           return d;
         };
+        b.bptr = up(bs.bptr);
+        b.brows = up(bs.brows);
+        b.iptr = up(bs.iptr);
+        b.irow = up(bs.irow);
         b.perm = up(bs.perm);
         b.slice_ptr = up(bs.slice_ptr);
         b.slice_nnz = up(bs.slice_nnz);
@@ -2052,25 +2075,31 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
         b.cnt = up(bs.cnt);
         b.ref4 = up(bs.ref4);
         b.valmap4 = up(bs.valmap4);
+        const size_t np = (size_t)bs.npad;
         if (pr == 0) {
-          b.diag64 = C->alloc<double>(n);
+          b.diag64 = C->alloc<double>(np);
           b.val64 = C->alloc<double>(std::max(bs.ell, 1));
-          b.val4_64 = C->alloc<double>((size_t)kNR * n);
+          b.val4_64 = C->alloc<double>((size_t)kNR * np);
         } else {
-          b.diag32 = C->alloc<float>(n);
+          b.diag32 = C->alloc<float>(np);
           b.val32 = C->alloc<float>(std::max(bs.ell, 1));
-          b.val4_32 = C->alloc<float>((size_t)kNR * n);
+          b.val4_32 = C->alloc<float>((size_t)kNR * np);
         }
         C->sync();  // host vectors go out of scope
       }
+    }
     if (const char *e = getenv("BNX_SF_WAVES")) C->sf_waves = atoi(e);  // tuning override of the solve window
     C->rp = C->alloc<int>(n + 1);
     C->ci = C->alloc<int>(nnz);
     C->val = C->alloc<double>(nnz);
     C->val32 = C->alloc<float>(nnz);
     C->ctl = C->alloc<DevCtl>(1);
-    C->blk_rhs = C->alloc<double>(n);
-    C->blk_xr = C->alloc<double>(n);
+    {
+      int np = n;
+      for (int dir = 0; dir < 2; dir++)
+        for (int pr = 0; pr < 2; pr++) np = std::max(np, C->blk[dir][pr].npad);
+      C->blk_rhs = C->alloc<double>(np);
+    }
     C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
     C->dflag = C->alloc<int>(4);
