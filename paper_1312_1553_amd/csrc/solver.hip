@@ -58,11 +58,24 @@ __device__ __forceinline__ T wsum(T v) {
 }
 
 // Deterministic reduction of D partial areas (part[d*nb + b]) into out[d], in a 256-thread block.
+// A lane keeps eight independent sums so that eight loads are in flight at once (the partials were
+// just written by workgroups on every XCD and are read from far memory); the summation order
+// depends on nb only.
 __device__ void reduce_parts(const double *part, int nb, int D, double *out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int d = w; d < D; d += 4) {
-    double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += part[(size_t)d * nb + b];
+    const double *p = part + (size_t)d * nb;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = lane;
+    for (; b + 7 * 64 < nb; b += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) v[u] = p[b + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 8; u++) a[u] += v[u];
+    }
+    for (int u = 0; b < nb; b += 64, u++) a[u & 7] += p[b];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = wsum(s);
     if (lane == 0) out[d] = s;
   }
@@ -2037,6 +2050,48 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     if (!v.empty()) throw ApiError{BNX_E_ARG, v};
     analyse(C->an);
     C->group = spmv_group((double)nnz / (double)n);
+    // SELL-64 copy for the SpMV when its padding stays small: slice s holds rows 64s..64s+63, entry e of
+    // lane l at ell_ptr[s] + 64 e + l; padding reads x[row] with weight 0
+    {
+      const int ns = (n + 63) / 64;
+      std::vector<int> eptr(ns + 1, 0), elen(ns, 0);
+      for (int sl = 0; sl < ns; sl++) {
+        int mx = 0;
+        for (int i = sl * 64; i < std::min<int>(n, sl * 64 + 64); i++) mx = std::max(mx, C->an.rp[i + 1] - C->an.rp[i]);
+        elen[sl] = mx;
+        eptr[sl + 1] = eptr[sl] + 64 * mx;
+      }
+      const long long esz = eptr[ns];
+      if (esz <= 5LL * nnz / 4 && esz < INT32_MAX && !getenv("BNX_NO_ELL")) {
+        std::vector<int> ecol(esz), emap(esz, -1);
+        for (int sl = 0; sl < ns; sl++)
+          for (int l = 0; l < 64; l++) {
+            const int i = sl * 64 + l;
+            for (int e = 0; e < elen[sl]; e++) {
+              const size_t at = (size_t)eptr[sl] + 64 * e + l;
+              const int q = i < n ? C->an.rp[i] + e : -1;
+              if (i < n && q < C->an.rp[i + 1]) {
+                ecol[at] = C->an.ci[q];
+                emap[at] = q;
+              } else {
+                ecol[at] = i < n ? i : 0;
+              }
+            }
+          }
+        C->ell_size = (int)esz;
+        C->ell_ptr = C->alloc<int>(ns + 1);
+        C->ell_len = C->alloc<int>(ns);
+        C->ell_col = C->alloc<int>(esz);
+        C->ell_map = C->alloc<int>(esz);
+        C->ell_v64 = C->alloc<double>(esz);
+        C->ell_v32 = C->alloc<float>(esz);
+        HIPCHK(hipMemcpyAsync(C->ell_ptr, eptr.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, C->st));
+        HIPCHK(hipMemcpyAsync(C->ell_len, elen.data(), sizeof(int) * ns, hipMemcpyHostToDevice, C->st));
+        HIPCHK(hipMemcpyAsync(C->ell_col, ecol.data(), sizeof(int) * esz, hipMemcpyHostToDevice, C->st));
+        HIPCHK(hipMemcpyAsync(C->ell_map, emap.data(), sizeof(int) * esz, hipMemcpyHostToDevice, C->st));
+        C->sync();  // host vectors go out of scope
+      }
+    }
     for (int pr = 0; pr < 2; pr++) {
       std::vector<int> prow, pstart;
       // Block size target: smaller blocks shorten the in-block chain latency per
