@@ -42,7 +42,7 @@ def counter_traffic(kname, n_grid):
     src = os.path.join(ROOT, "paper_1312_1553_amd", "csrc", "kernels.hip")
     if n_grid != 100 or not os.path.exists(path):
         return None
-    tag = "trsv_" + kname.split("_")[-1] if kname.startswith("trsv") else None
+    tag = ("trsv_" if kname.startswith("trsv") else "spmv_") + kname.split("_")[-1]
     sha, val = None, None
     for ln in open(path):
         if ln.startswith("kernels.hip sha256:"):
