@@ -403,6 +403,35 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
     bs.max_lds = std::max(bs.max_lds, bs.brows[b] + nimp + 1);
   }
   bs.nimp = bs.iptr[nb];
+  // exports: imported rows, numbered block by block in rank order
+  std::vector<int> exp_id(n, -1);
+  for (int e = 0; e < bs.nimp; e++) exp_id[bs.irow[e]] = 0;
+  bs.eptr.assign(nb + 1, 0);
+  bs.erank.clear();
+  for (int b = 0; b < nb; b++) {
+    for (int k = bs.bptr[b]; k < bs.bptr[b] + bs.brows[b]; k++)
+      if (exp_id[bs.perm[k]] == 0) {
+        exp_id[bs.perm[k]] = (int)bs.erank.size() + 1;  // 1-based while numbering
+        bs.erank.push_back(k - bs.bptr[b]);
+      }
+    bs.eptr[b + 1] = (int)bs.erank.size();
+  }
+  bs.nexp = (int)bs.erank.size();
+  bs.isrc.resize(bs.nimp);
+  for (int e = 0; e < bs.nimp; e++) bs.isrc[e] = exp_id[bs.irow[e]] - 1;
+  // output order: each block's rows by increasing row index
+  bs.orow.assign(npad, 0);
+  bs.oslot.assign(npad, 0);
+  for (int b = 0; b < nb; b++) {
+    std::vector<std::pair<int, int>> o;
+    o.reserve(bs.brows[b]);
+    for (int t = 0; t < bs.brows[b]; t++) o.push_back({bs.perm[bs.bptr[b] + t], t});
+    std::sort(o.begin(), o.end());
+    for (int t = 0; t < bs.brows[b]; t++) {
+      bs.orow[bs.bptr[b] + t] = o[t].first;
+      bs.oslot[bs.bptr[b] + t] = o[t].second;
+    }
+  }
 }
 
 }  // namespace bnx

@@ -65,9 +65,14 @@ struct Levels {
 // index in that order: block b occupies ranks bptr[b] .. bptr[b]+brows[b]-1,
 // padded up to a multiple of 64 (padding ranks: cnt 0, perm -1).
 // A block keeps every value it reads in LDS: its own rows at their local rank,
-// and the rows it needs from earlier blocks ("imports": irow[iptr[b] ..
-// iptr[b+1]-1], original row ids in order of first use) at brows[b] + import
-// index, followed by one slot that holds 0.  The first kNR dependencies of
+// and the rows it needs from earlier blocks ("imports": iptr[b] .. iptr[b+1]-1,
+// in order of first use) at brows[b] + import index, followed by one slot that
+// holds 0.  Rows read by later blocks ("exports") travel through a compact
+// buffer: block b publishes its exports, in rank order, at export ids
+// eptr[b] .. eptr[b+1]-1 (erank: their local ranks), and an import names the
+// export id it reads (isrc).  The solution itself is written once per block,
+// in row order: orow / oslot list the block's rows by increasing row index with
+// their local ranks.  The first kNR dependencies of
 // rank k are at [q * npad + k] of ref4 / valmap4 (q < kNR), encoded as
 // -(LDS slot)-1; unused ones point at the zero slot with valmap -1 (weight 0),
 // so a row always reads kNR values.  Further dependencies of long rows are
@@ -87,6 +92,11 @@ struct BlockSched {
   std::vector<int> brows;      // nblocks: rows of each block
   std::vector<int> iptr;       // nblocks+1: imports of each block
   std::vector<int> irow;       // imported rows (original ids), in order of first use
+  std::vector<int> isrc;       // export id of each import
+  std::vector<int> eptr;       // nblocks+1: exports of each block
+  std::vector<int> erank;      // local rank of each export
+  std::vector<int> orow, oslot;  // npad: rows of each block by increasing row index, and their local ranks
+  int nexp = 0;
   std::vector<int> perm;       // npad: original row of rank k (-1: padding)
   std::vector<int> diagmap;    // npad: factor value index of the diagonal of row perm[k]
   std::vector<int> cnt;        // npad: number of dependencies of rank k (| kLongSlice)
@@ -142,7 +152,9 @@ struct Mat {
 template <typename T>
 struct DevBlk {
   int n = 0, npad = 0, nblocks = 0;
-  const int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *irow = nullptr;
+  int nexp = 0;
+  const int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *isrc = nullptr;
+  const int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
   const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
   const int *cnt = nullptr, *ref4 = nullptr;
   const T *diag = nullptr, *val = nullptr, *val4 = nullptr;  // diag holds reciprocals
@@ -152,6 +164,7 @@ template <typename T>
 struct Tri {
   DevBlk<T> blk;
   void *blk_scratch = nullptr;  // npad values: right-hand side in rank order
+  void *blk_exp = nullptr;      // nexp values: exported rows (polled by the blocks that import them)
   int n = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;

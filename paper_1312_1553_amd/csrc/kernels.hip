@@ -384,12 +384,13 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
 
 // First launch of the LDS-staged solve.  part & 1: right-hand side in rank
 // order, bp[k] = b_i - sum_t coef[t] R_t[i] for i = perm[k] (0 on padding ranks);
-// part & 2: sentinel fill of the solution x (every value a block imports is
-// polled in x until it leaves the sentinel state) and reset of the ticket counter.
+// part & 2: sentinel fill of the export buffer xe (every value a block imports
+// is polled there until it leaves the sentinel state) and reset of the ticket
+// counter.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int n, int npad, const int *__restrict__ perm,
+__global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int nexp, int npad, const int *__restrict__ perm,
                                                       const T *__restrict__ b, int kfuse, VList<T> R,
-                                                      const double *coef, T *bp, T *x, int *counter,
+                                                      const double *coef, T *bp, T *xe, int *counter,
                                                       const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
@@ -399,8 +400,8 @@ __global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int n, int npad,
       bp[k] = i >= 0 ? rhs_value(i, b, kfuse, R, coef) : T(0);
     }
   if (part & 2) {
-    U *xu = reinterpret_cast<U *>(x);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
+    U *xu = reinterpret_cast<U *>(xe);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nexp; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
   }
 }
@@ -446,7 +447,7 @@ __device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k
 // unfinished row can always proceed.  Waits are bounded: on overflow the value
 // becomes NaN and *err is set.
 template <typename T, int CAP>
-__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, int *counter,
+__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xe, int *counter,
                                                     int *err, const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
@@ -464,25 +465,25 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   const int i0 = F.iptr[blk], nimp = F.iptr[blk + 1] - i0;
   for (int i = threadIdx.x; i <= nrow + nimp; i += 1024) xs[i] = i < nrow + nimp ? Sentinel<T>::bits : U(0);
   __syncthreads();
-  U *xu = reinterpret_cast<U *>(x);
+  U *xeu = reinterpret_cast<U *>(xe);
   const int nsl = (nrow + 63) >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
   if (wave >= WC + WP) {  // importer: two imports per lane in flight, the next two rows prefetched
     const int step = WI * 128;
     int base = (wave - WC - WP) * 128;
-    int r0 = base + lane < nimp ? F.irow[i0 + base + lane] : -1;
-    int r1 = base + 64 + lane < nimp ? F.irow[i0 + base + 64 + lane] : -1;
+    int r0 = base + lane < nimp ? F.isrc[i0 + base + lane] : -1;
+    int r1 = base + 64 + lane < nimp ? F.isrc[i0 + base + 64 + lane] : -1;
     for (; base < nimp; base += step) {
       const int e0 = base + lane, e1 = base + 64 + lane;
-      const int n0 = base + step + lane < nimp ? F.irow[i0 + base + step + lane] : -1;
-      const int n1 = base + step + 64 + lane < nimp ? F.irow[i0 + base + step + 64 + lane] : -1;
+      const int n0 = base + step + lane < nimp ? F.isrc[i0 + base + step + lane] : -1;
+      const int n1 = base + step + 64 + lane < nimp ? F.isrc[i0 + base + step + 64 + lane] : -1;
       bool p0 = r0 >= 0, p1 = r1 >= 0;
       int spins = 0;
       while (__builtin_amdgcn_ballot_w64(p0 || p1) != 0ull) {
         if (p0 || p1) {
-          U u0 = p0 ? __hip_atomic_load(&xu[r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
-          U u1 = p1 ? __hip_atomic_load(&xu[r1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
+          U u0 = p0 ? __hip_atomic_load(&xeu[r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
+          U u1 = p1 ? __hip_atomic_load(&xeu[r1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : Sentinel<T>::bits;
           if (++spins > kSpinLimit) {  // bounded wait: pending imports become NaN
             const U nan = to_bits<T>(T(__builtin_nan("")));
             if (u0 == Sentinel<T>::bits) u0 = nan;
@@ -503,24 +504,23 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
       r0 = n0;
       r1 = n1;
     }
-    return;
-  }
-
-  if (wave >= WC) {  // publisher: PG slices at a time, each value goes out as soon as it is in LDS
+  } else if (wave >= WC) {
+    // publisher: the block's exports, PG per lane in flight, each value goes out as soon as it is in LDS
     constexpr int PG = 4;
-    const int p = wave - WC;
-    // own slices are p, p + WP, p + 2 WP, ...; group j holds own slices j*PG .. j*PG+PG-1
-    auto group_rows = [&](int j, int (&r)[PG]) {
+    const int e0 = F.eptr[blk], nex = F.eptr[blk + 1] - e0;
+    const int p = wave - WC, gstep = WP * 64 * PG;
+    // group j of publisher p: exports e0 + p*64*PG + j*gstep + g*64 + lane, g < PG
+    auto group_slots = [&](int j, int (&r)[PG]) {
 #pragma unroll
       for (int g = 0; g < PG; g++) {
-        const int sl = p + WP * (j * PG + g), t = (sl << 6) + lane;
-        r[g] = (sl < nsl && t < nrow) ? F.perm[k0 + t] : -1;
+        const int e = p * 64 * PG + j * gstep + g * 64 + lane;
+        r[g] = e < nex ? F.erank[e0 + e] : -1;
       }
     };
     int cur[PG], nxt[PG];
-    group_rows(0, cur);
-    for (int j = 0; p + WP * j * PG < nsl; j++) {
-      group_rows(j + 1, nxt);
+    group_slots(0, cur);
+    for (int j = 0; p * 64 * PG + j * gstep < nex; j++) {
+      group_slots(j + 1, nxt);
       unsigned pend = 0;
 #pragma unroll
       for (int g = 0; g < PG; g++) pend |= (cur[g] >= 0 ? 1u : 0u) << g;
@@ -529,11 +529,9 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
         if (pend) {
           U u[PG];
 #pragma unroll
-          for (int g = 0; g < PG; g++) {
-            const int t = ((p + WP * (j * PG + g)) << 6) + lane;
-            u[g] = (pend >> g & 1u) ? __hip_atomic_load(&xs[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+          for (int g = 0; g < PG; g++)
+            u[g] = (pend >> g & 1u) ? __hip_atomic_load(&xs[cur[g]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
                                     : Sentinel<T>::bits;
-          }
           const bool over = ++spins > kSpinLimit;
           if (over) atomicOr(err, 1);
 #pragma unroll
@@ -542,7 +540,8 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
               U v = u[g];
               if (v == Sentinel<T>::bits && over) v = to_bits<T>(T(__builtin_nan("")));
               if (v != Sentinel<T>::bits) {
-                __hip_atomic_store(&xu[cur[g]], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int e = p * 64 * PG + j * gstep + g * 64 + lane;
+                __hip_atomic_store(&xeu[e0 + e], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 pend &= ~(1u << g);
               }
             }
@@ -552,9 +551,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
 #pragma unroll
       for (int g = 0; g < PG; g++) cur[g] = nxt[g];
     }
-    return;
-  }
-
+  } else {
   // compute: row data of the next three slices in flight while one is solved;
   // the four buffers rotate statically (no register copies, which would wait on
   // the loads in flight)
@@ -684,12 +681,16 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     fetch(sl + 6 * WC, C);
     solve_slice(D, sl + 3 * WC);
   }
+  }
+  // every row of the block is in LDS: write the solution once, in row order
+  __syncthreads();
+  for (int t = threadIdx.x; t < nrow; t += 1024) x[F.orow[k0 + t]] = from_bits<T>(xs[F.oslot[k0 + t]]);
 }
 
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  hipLaunchKernelGGL((k_trsv_blk<T, CAP>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x, L.counter,
-                     &L.ctl->err, gate);
+  hipLaunchKernelGGL((k_trsv_blk<T, CAP>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+                     reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
 }
 
 template <typename T>
@@ -700,12 +701,8 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
     hipEvent_t ev0 = nullptr;
     T *bp = reinterpret_cast<T *>(F.blk_scratch);
     const int nb = grid_for((size_t)F.blk.npad, kNBMax);
-    // a right-hand side that aliases the solution is read completely before the sentinel fill
-    const bool alias = (const void *)b == (const void *)x;
-    const int parts[2] = {alias ? 1 : 3, 2};
-    for (int q = 0; q < (alias ? 2 : 1); q++)
-      hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, parts[q], F.n, F.blk.npad, F.blk.perm,
-                         b, kfuse, R, coef, bp, x, L.counter, gate);
+    hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, 3, F.blk.nexp, F.blk.npad, F.blk.perm, b,
+                       kfuse, R, coef, bp, reinterpret_cast<T *>(F.blk_exp), L.counter, gate);
     if (prof0) L.prof->begin(L.st, &ev0);
     if constexpr (sizeof(T) == 8) launch_blk<T, kLdsCap64>(L, F, bp, x, gate);
     else launch_blk<T, kLdsCap32>(L, F, bp, x, gate);

@@ -827,14 +827,16 @@ struct bnx_ctx {
   float *Lv32 = nullptr, *Ltv32 = nullptr;
   // block schedules of the LDS-staged solve: [0] forward (L), [1] backward (L^T); per precision
   struct BlkDev {
-    int n = 0, npad = 0, nblocks = 0, ell = 0;
-    int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *irow = nullptr;
+    int n = 0, npad = 0, nblocks = 0, ell = 0, nexp = 0;
+    int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *isrc = nullptr;
+    int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
     int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
     int *valmap = nullptr, *diagmap = nullptr, *cnt = nullptr, *ref4 = nullptr, *valmap4 = nullptr;
     double *diag64 = nullptr, *val64 = nullptr, *val4_64 = nullptr;
     float *diag32 = nullptr, *val32 = nullptr, *val4_32 = nullptr;
   } blk[2][2];  // [direction][0 = fp64 LDS capacity, 1 = fp32 LDS capacity]
   double *blk_rhs = nullptr;  // right-hand side of a block solve in rank order (largest npad)
+  double *blk_exp = nullptr;  // export buffer of a block solve (largest nexp)
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -942,10 +944,15 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.n = b.n;
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
+    F.blk.nexp = b.nexp;
     F.blk.bptr = b.bptr;
     F.blk.brows = b.brows;
     F.blk.iptr = b.iptr;
-    F.blk.irow = b.irow;
+    F.blk.isrc = b.isrc;
+    F.blk.eptr = b.eptr;
+    F.blk.erank = b.erank;
+    F.blk.orow = b.orow;
+    F.blk.oslot = b.oslot;
     F.blk.perm = b.perm;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
@@ -957,6 +964,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.val4 = b.val4_64;
   }
   F.blk_scratch = blk_rhs;
+  F.blk_exp = blk_exp;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -977,10 +985,15 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.n = b.n;
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
+    F.blk.nexp = b.nexp;
     F.blk.bptr = b.bptr;
     F.blk.brows = b.brows;
     F.blk.iptr = b.iptr;
-    F.blk.irow = b.irow;
+    F.blk.isrc = b.isrc;
+    F.blk.eptr = b.eptr;
+    F.blk.erank = b.erank;
+    F.blk.orow = b.orow;
+    F.blk.oslot = b.oslot;
     F.blk.perm = b.perm;
     F.blk.slice_ptr = b.slice_ptr;
     F.blk.slice_nnz = b.slice_nnz;
@@ -992,6 +1005,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.val4 = b.val4_32;
   }
   F.blk_scratch = blk_rhs;
+  F.blk_exp = blk_exp;
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -2111,6 +2125,7 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
         b.npad = bs.npad;
         b.nblocks = bs.nblocks;
         b.ell = bs.ell;
+        b.nexp = bs.nexp;
         auto up = [&](const std::vector<int> &v) {
           int *d = C->alloc<int>(std::max<size_t>(v.size(), 1));
           if (!v.empty())
@@ -2120,7 +2135,11 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
         b.bptr = up(bs.bptr);
         b.brows = up(bs.brows);
         b.iptr = up(bs.iptr);
-        b.irow = up(bs.irow);
+        b.isrc = up(bs.isrc);
+        b.eptr = up(bs.eptr);
+        b.erank = up(bs.erank);
+        b.orow = up(bs.orow);
+        b.oslot = up(bs.oslot);
         b.perm = up(bs.perm);
         b.slice_ptr = up(bs.slice_ptr);
         b.slice_nnz = up(bs.slice_nnz);
@@ -2154,6 +2173,10 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
       for (int dir = 0; dir < 2; dir++)
         for (int pr = 0; pr < 2; pr++) np = std::max(np, C->blk[dir][pr].npad);
       C->blk_rhs = C->alloc<double>(np);
+      int ne = 1;
+      for (int dir = 0; dir < 2; dir++)
+        for (int pr = 0; pr < 2; pr++) ne = std::max(ne, C->blk[dir][pr].nexp);
+      C->blk_exp = C->alloc<double>(ne);
     }
     C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
