@@ -83,7 +83,9 @@ constexpr int kLongSlice = 1 << 30;  // flag in cnt: the rank's slice has rows l
 // LDS values per block (rows + imports + the zero slot): 159 KiB of the 160 KiB of a CU.
 constexpr int kLdsCap64 = 20352;
 constexpr int kLdsCap32 = 40704;
-constexpr int kBlkTarget = 3584;  // default LDS values per block of the partition
+// default LDS values per block of the partition (measured on the 7-point 100^3 grid)
+constexpr int kBlkTarget64 = 7168;
+constexpr int kBlkTarget32 = 12288;
 
 struct BlockSched {
   int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;

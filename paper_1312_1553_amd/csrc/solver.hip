@@ -2108,10 +2108,10 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     }
     for (int pr = 0; pr < 2; pr++) {
       std::vector<int> prow, pstart;
-      // Block size target: smaller blocks shorten the in-block chain latency per
-      // level, larger ones cross fewer block boundaries; measured best near 3.5k
-      // rows on the 7-point 100^3 grid in both precisions.
-      int cap = kBlkTarget;
+      // Block size target: larger blocks cross fewer block boundaries, smaller ones
+      // keep more waves per level busy; measured best near 7k (FP64) and 12k (FP32)
+      // rows on the 7-point 100^3 grid.
+      int cap = pr == 0 ? kBlkTarget64 : kBlkTarget32;
       if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
         cap = atoi(e);
       cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
