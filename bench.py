@@ -240,7 +240,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": counter_traffic(kname, N),
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
-                     "levels": levels},
+                     "levels": levels,
+                     "limiter": ("latency: a chain of %d dependent levels" % levels) if kname.startswith("trsv")
+                     else "hbm"},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
