@@ -365,13 +365,22 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
   bs.irow.clear();
   bs.max_lds = 0;
   std::vector<int> imp_blk(n, -1), imp_slot(n, 0);
+  std::vector<int> order;
   for (int b = 0; b < nb; b++) {
     int nimp = 0;
     for (int k = bs.bptr[b]; k < bs.bptr[b] + bs.brows[b]; k++) {
       int e0, e1;
       deps(bs.perm[k], e0, e1);
       const int sl = k / 64, lane = k % 64;
-      for (int q = e0, e = 0; q < e1; q++, e++) {
+      // dependencies by level: the ones that finish first come first, so a row consumes its
+      // entries as they arrive and the last to arrive is read last
+      order.resize(e1 - e0);
+      for (int q = e0; q < e1; q++) order[q - e0] = q;
+      std::sort(order.begin(), order.end(), [&](int a, int c) {
+        return glev[ci[a]] != glev[ci[c]] ? glev[ci[a]] < glev[ci[c]] : a < c;
+      });
+      for (int e = 0; e < e1 - e0; e++) {
+        const int q = order[e];
         const int j = ci[q];
         int slot;
         if (blk[j] == b) {

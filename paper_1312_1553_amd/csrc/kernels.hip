@@ -573,6 +573,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
       // zero slot): read all NR values each round, finish when none is a sentinel
       int spins = 0;
       while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
+        const bool fin0 = fin;
         if (!fin) {
           U u[NR];
 #pragma unroll
@@ -595,54 +596,75 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
           atomicOr(err, 1);
           fin = true;
         }
+        if (BNX_TRSV_SLEEP > 0 && __builtin_amdgcn_ballot_w64(fin != fin0) == 0ull)
+          __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
       }
       return;
     }
-    const int nlong = cur.cnt & ~kLongSlice;  // entries beyond NR come from the ELL slices
-    const int nown = nlong < NR ? nlong : NR;
+    // general path: the first NR dependencies (unused slots read the zero slot), then the
+    // rest from the ELL slices in chunks of KC independent loads, consumed in order
+    constexpr int KC = sizeof(T) == 8 ? 4 : 8;
+    const int nlong = cur.cnt & ~kLongSlice;
     const int esp = F.slice_ptr[gsl] + lane;
-    const unsigned need = (1u << nown) - 1u;
-    T xv[NR];
+    int cr[KC];
+    T cv[KC];
+    int e = NR;                // next ELL entry to load
+    int cpos = KC, cend = KC;  // consumed / valid entries of the chunk in registers
+    auto load_chunk = [&]() {
+      const int m = nlong - e < KC ? nlong - e : KC;
 #pragma unroll
-    for (int q = 0; q < NR; q++) xv[q] = T(0);
-    unsigned seen = 0;
-    bool cached_done = false;
+      for (int q = 0; q < KC; q++) {
+        const int at = esp + 64 * (e + q - NR);
+        cr[q] = q < m ? F.ref[at] : -1;
+        cv[q] = q < m ? F.val[at] : T(0);
+      }
+      e += m;
+      cpos = 0;
+      cend = m;
+    };
+    if (!fin && nlong > NR) load_chunk();  // in flight while the first NR are polled
+    bool head = false;                     // the first NR are consumed
     T s = cur.s;
-    int e = NR, spins = 0;
+    int spins = 0;
     while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
-      const unsigned seen0 = seen;
-      const bool fin0 = fin;
       if (!fin) {
-        const unsigned pend = need & ~seen;
-        if (pend) {
+        if (!head) {
           U lv[NR];
 #pragma unroll
-          for (int q = 0; q < NR; q++)  // all polls issued before any result is examined
-            lv[q] = (pend >> q & 1u)
-                        ? __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                        : Sentinel<T>::bits;
-#pragma unroll
           for (int q = 0; q < NR; q++)
-            if ((pend >> q & 1u) && lv[q] != Sentinel<T>::bits) {
-              xv[q] = from_bits<T>(lv[q]);
-              seen |= 1u << q;
-            }
-        }
-        if (seen == need) {
-          if (!cached_done) {
+            lv[q] = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          bool ok = true;
 #pragma unroll
-            for (int q = 0; q < NR; q++) s -= cur.vv[q] * xv[q];
-            cached_done = true;
+          for (int q = 0; q < NR; q++) ok = ok && lv[q] != Sentinel<T>::bits;
+          if (ok) {
+#pragma unroll
+            for (int q = 0; q < NR; q++) s -= cur.vv[q] * from_bits<T>(lv[q]);
+            head = true;
           }
-          // rows longer than the register cache: the remaining entries in order
-          while (e < nlong) {
-            const int at = esp + 64 * (e - NR);
-            const U u = __hip_atomic_load(&xs[-F.ref[at] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (u == Sentinel<T>::bits) break;
-            s -= F.val[at] * from_bits<T>(u);
-            e++;
+        }
+        if (head) {
+          for (;;) {
+            if (cpos == cend) {
+              if (e >= nlong) break;
+              load_chunk();
+            }
+            U u[KC];
+#pragma unroll
+            for (int q = 0; q < KC; q++)
+              u[q] = (q >= cpos && q < cend)
+                         ? __hip_atomic_load(&xs[-cr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                         : Sentinel<T>::bits;
+            int c = cpos;
+#pragma unroll
+            for (int q = 0; q < KC; q++)  // the ready prefix, in entry order
+              if (q == c && q < cend && u[q] != Sentinel<T>::bits) {
+                s -= cv[q] * from_bits<T>(u[q]);
+                c++;
+              }
+            cpos = c;
+            if (cpos < cend) break;  // blocked: poll again next round
           }
-          if (e >= nlong) {
+          if (cpos == cend && e >= nlong) {
             __hip_atomic_store(&xs[t], to_bits<T>(s * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             fin = true;
           }
@@ -653,14 +675,6 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
           atomicOr(err, 1);
           fin = true;
         }
-      }
-      // a round without progress yields the SIMD to the other waves; a round that
-      // stored values wakes the waves of the workgroup that sleep
-      const bool moved = fin != fin0 || seen != seen0;
-      if (__builtin_amdgcn_ballot_w64(moved) == 0ull) {
-        if (BNX_TRSV_SLEEP > 0) __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
-      } else if (BNX_TRSV_WAKE && __builtin_amdgcn_ballot_w64(fin != fin0) != 0ull) {
-        __asm__ volatile("s_wakeup");
       }
     }
   };
