@@ -82,6 +82,9 @@ def kernel_probe(args, A, S, nnzL, bnx, torch):
         byt = spmv_bytes(A.n, A.nnz, vb[prec])
         print(f"[kernels] spmv {'f64' if prec == 0 else 'f32'}: {cnt} launches, avg {us:.1f} us, "
               f"{byt / us / 1e3:.1f} GB/s algorithmic", flush=True)
+    for kind, hops, what in ((0, 8192, "LDS hand-over between waves"), (1, 4096, "global flag between workgroups")):
+        us = bnx.bnx_probe_latency(S.h, kind, hops)
+        print(f"[kernels] latency probe, {what}: {us * 1000:.0f} ns per hop ({hops} hops)", flush=True)
     src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -137,6 +140,12 @@ def main():
     if args.kernels:
         kernel_probe(args, A, S, nnzL, bnx, torch)
         return
+
+    # latency roofline of the triangular solves: chained hand-overs measured on this device
+    t_lds = bnx.bnx_probe_latency(S.h, 0, 8192)
+    t_glb = bnx.bnx_probe_latency(S.h, 1, 4096)
+    print(f"[bench] latency probe: {t_lds * 1000:.0f} ns per LDS hand-over, {t_glb * 1000:.0f} ns per global one",
+          flush=True)
 
     results = {}
     for name, prec in (("mixed", bnx.MIXED), ("fp64", bnx.FP64)):
@@ -242,7 +251,10 @@ def main():
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                      "levels": levels,
                      "limiter": ("latency: a chain of %d dependent levels" % levels) if kname.startswith("trsv")
-                     else "hbm"},
+                     else "hbm",
+                     "latency": {"t_lds_hop_us": round(t_lds, 4), "t_global_hop_us": round(t_glb, 4),
+                                 "floor_us": round(levels * t_lds, 2),
+                                 "frac": round(levels * t_lds / (avg_s * 1e6), 4)}},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

@@ -236,6 +236,19 @@ bnx_status bnx_set_trsv_mode(bnx_ctx *ctx, int mode);
 bnx_status bnx_set_profiling(bnx_ctx *ctx, int on);
 bnx_status bnx_kernel_time(bnx_ctx *ctx, int kernel, double *ms_total, long long *launches);
 
+/* Latency probe on the context's device: a chain of `hops` dependent
+ * hand-overs (2 <= hops <= 65536), timed with HIP events as one launch.
+ * kind 0: between the 16 waves of one workgroup through an LDS flag (the
+ * in-block dependency of the LDS-staged triangular solve); kind 1: between
+ * workgroups, each polling its predecessor's device-scope flag in global
+ * memory (the dependency between two blocks).  The triangular solves are
+ * bounded below by levels x the kind-0 figure, which is the latency roofline
+ * reported beside the bandwidth one.  *us_per_hop receives microseconds per
+ * hand-over.  Waits are bounded: BNX_E_BREAKDOWN if one overflows; BNX_E_ARG
+ * on a bad kind or hop count.  The flag buffer (256 KiB) is allocated by the
+ * context on first use. */
+bnx_status bnx_probe_latency(bnx_ctx *ctx, int kind, int hops, double *us_per_hop);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,7 +58,7 @@ class Stats(C.Structure):
 EXPORTS = ["bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_create_csr", "bnx_set_values", "bnx_factor",
            "bnx_solve", "bnx_backward", "bnx_set_adjoint_params", "bnx_last_error", "bnx_destroy", "bnx_spmv",
            "bnx_ic_apply", "bnx_prec_apply", "bnx_correction_solve", "bnx_dacg", "bnx_set_trsv_mode",
-           "bnx_set_profiling", "bnx_kernel_time"]
+           "bnx_set_profiling", "bnx_kernel_time", "bnx_probe_latency"]
 
 _lib = None
 _vp = C.c_void_p
@@ -96,6 +96,7 @@ def load(path: str = LIBPATH):
     L.bnx_set_trsv_mode.argtypes = [_vp, C.c_int]
     L.bnx_set_profiling.argtypes = [_vp, C.c_int]
     L.bnx_kernel_time.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+    L.bnx_probe_latency.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
     for f in EXPORTS:
         if f not in ("bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_last_error", "bnx_destroy"):
             getattr(L, f).restype = C.c_int
@@ -198,6 +199,13 @@ def bnx_dacg(h, precision, m, Qt, x0, tol, itmax, x):
 
 def bnx_set_trsv_mode(h, mode):
     return _check(h, load().bnx_set_trsv_mode(h, mode))
+
+
+def bnx_probe_latency(h, kind, hops):
+    """Microseconds per dependent hand-over: kind 0 LDS between waves, 1 global flag between workgroups."""
+    us = C.c_double()
+    _check(h, load().bnx_probe_latency(h, int(kind), int(hops), C.byref(us)))
+    return us.value
 
 
 def bnx_set_profiling(h, on):

@@ -16,6 +16,7 @@ constexpr int kNBMax = 2048;   // blocks of a streaming kernel (partials per dot
 constexpr int kPartSlots = 80; // dots per partial area
 constexpr int kAreas = 10;     // partial areas
 constexpr int kBlock = 256;
+constexpr int kProbeHopsMax = 65536;  // longest chain of the latency probes
 
 // Pointer list passed by value to kernels.
 template <typename T>
@@ -265,5 +266,7 @@ template <typename Tin, typename Tout>
 void launch_cast(hipStream_t st, size_t n, const Tin *in, Tout *out);
 template <typename T>
 void launch_fill(hipStream_t st, size_t n, T *x, T v);
+// Latency probes (kind 0: LDS hand-over between waves, 1: global flag between workgroups).
+void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, int *err);
 
 }  // namespace bnx

@@ -701,6 +701,57 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   for (int t = threadIdx.x; t < nrow; t += 1024) x[F.orow[k0 + t]] = from_bits<T>(xs[F.oslot[k0 + t]]);
 }
 
+// Latency probes: a chain of `hops` dependent hand-overs, timed as one launch.
+// k_probe_lds: one workgroup; hop h is taken by wave h mod 16, which waits until
+// the LDS flag holds h-1 and then writes h (the same hand-over as a dependency
+// between two compute waves of the block solve).  k_probe_global: one
+// workgroup per hop in ticket order; each waits for its predecessor's
+// device-scope flag in global memory and then sets its own (the hand-over
+// between two blocks).  Waits are bounded; on overflow *err is set.
+__global__ __launch_bounds__(1024) void k_probe_lds(int hops, int *err) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = -1;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int h = wave; h < hops; h += 16) {
+    int spins = 0;
+    while (__hip_atomic_load(&flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != h - 1) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicOr(err, 1);
+        break;
+      }
+    }
+    if (lane == 0) __hip_atomic_store(&flag, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_probe_global(int *flags, int *counter, int *err) {
+  __shared__ int ticket;
+  if (threadIdx.x == 0) ticket = atomicAdd(counter, 1);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int me = ticket;
+  if (me > 0) {
+    int spins = 0;
+    while (__hip_atomic_load(&flags[me - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      if (++spins > kSpinLimit) {
+        atomicOr(err, 1);
+        break;
+      }
+  }
+  __hip_atomic_store(&flags[me], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, int *err) {
+  if (kind == 0) {
+    hipLaunchKernelGGL(k_probe_lds, dim3(1), dim3(1024), 0, st, hops, err);
+  } else {
+    launch_fill<int>(st, (size_t)hops, flags, 0);
+    launch_fill<int>(st, 1, counter, 0);
+    hipLaunchKernelGGL(k_probe_global, dim3(hops), dim3(64), 0, st, flags, counter, err);
+  }
+}
+
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
   hipLaunchKernelGGL((k_trsv_blk<T, CAP>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,

@@ -837,6 +837,7 @@ struct bnx_ctx {
   } blk[2][2];  // [direction][0 = fp64 LDS capacity, 1 = fp32 LDS capacity]
   double *blk_rhs = nullptr;  // right-hand side of a block solve in rank order (largest npad)
   double *blk_exp = nullptr;  // export buffer of a block solve (largest nexp)
+  int *probe_flags = nullptr;  // latency probe flags (allocated on first use)
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -2296,6 +2297,30 @@ bnx_status bnx_kernel_time(bnx_ctx *C, int kernel, double *ms_total, long long *
     C->prof.drain();
     *ms_total = C->prof.ms[kernel];
     *launches = C->prof.count[kernel];
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_probe_latency(bnx_ctx *C, int kind, int hops, double *us_per_hop) {
+  if (!C || kind < 0 || kind > 1 || hops < 2 || hops > kProbeHopsMax || !us_per_hop) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->probe_flags) C->probe_flags = C->alloc<int>(kProbeHopsMax);
+    HIPCHK(hipMemsetAsync(&C->ctl->err, 0, sizeof(int), C->st));
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    launch_probe(C->st, kind, 2, C->probe_flags, C->counter + 1, &C->ctl->err);  // warm-up
+    HIPCHK(hipEventRecord(a, C->st));
+    launch_probe(C->st, kind, hops, C->probe_flags, C->counter + 1, &C->ctl->err);
+    HIPCHK(hipEventRecord(b, C->st));
+    HIPCHK(hipGetLastError());
+    C->sync();
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (C->readctl().err) throw ApiError{BNX_E_BREAKDOWN, "latency probe wait bound exceeded"};
+    *us_per_hop = 1000.0 * ms / hops;
     return BNX_OK;
   });
 }

@@ -354,3 +354,17 @@ def test_autograd_chain_matches_torch_eigh():
     loss.backward()
     got = host(lkg.grad)
     np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9)
+
+
+def test_latency_probe():
+    A = mats()["laplace2d_32"]
+    S = solver_for(A)
+    for kind in (0, 1):
+        us = bnx.bnx_probe_latency(S.h, kind, 1024)
+        say("case latency probe", kind, us)
+        assert 0.0 < us < 50.0
+    with pytest.raises(bnx.BnxError):
+        bnx.bnx_probe_latency(S.h, 2, 1024)
+    with pytest.raises(bnx.BnxError):
+        bnx.bnx_probe_latency(S.h, 0, 1)
+    S.close()
