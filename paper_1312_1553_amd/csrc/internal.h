@@ -155,7 +155,7 @@ struct Mat {
 template <typename T>
 struct DevBlk {
   int n = 0, npad = 0, nblocks = 0;
-  int nexp = 0;
+  int nexp = 0, ell = 0;  // ell: entries in the ELL slices (0: no row has more than kNR dependencies)
   const int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *isrc = nullptr;
   const int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
   const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;

@@ -315,6 +315,9 @@ constexpr int kSpinLimit = 1 << 20;
 #ifndef BNX_TRSV_WI
 #define BNX_TRSV_WI 2
 #endif
+#ifndef BNX_TRSV_KC32
+#define BNX_TRSV_KC32 8
+#endif
 #ifndef BNX_TRSV_PUBSLEEP
 #define BNX_TRSV_PUBSLEEP 1
 #endif
@@ -446,7 +449,7 @@ __device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k
 // Every dependency of a row has a lower rank or is an import, so the lowest
 // unfinished row can always proceed.  Waits are bounded: on overflow the value
 // becomes NaN and *err is set.
-template <typename T, int CAP>
+template <typename T, int CAP, bool LONG>
 __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xe, int *counter,
                                                     int *err, const int *gate) {
   if (gate && *gate) return;
@@ -567,8 +570,9 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     const int t = (sl << 6) + lane;
     bool fin = t >= nrow;
     const int gsl = (k0 >> 6) + sl;
-    // lane 0 always holds a row of the slice; its flag tells whether any row is long
-    if ((__builtin_amdgcn_readfirstlane(cur.cnt) & kLongSlice) == 0) {
+    // lane 0 always holds a row of the slice; its flag tells whether any row is long (schedules
+    // without long rows run the instantiation that has no general path)
+    if (!LONG || (__builtin_amdgcn_readfirstlane(cur.cnt) & kLongSlice) == 0) {
       // every row of the slice has at most NR dependencies (unused ones read the
       // zero slot): read all NR values each round, finish when none is a sentinel
       int spins = 0;
@@ -601,9 +605,10 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
       }
       return;
     }
+    if constexpr (LONG) {
     // general path: the first NR dependencies (unused slots read the zero slot), then the
     // rest from the ELL slices in chunks of KC independent loads, consumed in order
-    constexpr int KC = sizeof(T) == 8 ? 4 : 8;
+    constexpr int KC = sizeof(T) == 8 ? 4 : BNX_TRSV_KC32;
     const int nlong = cur.cnt & ~kLongSlice;
     const int esp = F.slice_ptr[gsl] + lane;
     int cr[KC];
@@ -676,6 +681,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
           fin = true;
         }
       }
+    }
     }
   };
   RowPre<T, NR> A, B, C, D;
@@ -754,8 +760,12 @@ void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, 
 
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  hipLaunchKernelGGL((k_trsv_blk<T, CAP>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
-                     reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
+  if (F.blk.ell > 0)
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, true>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
+  else
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
 }
 
 template <typename T>

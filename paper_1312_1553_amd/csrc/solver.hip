@@ -946,6 +946,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
     F.blk.nexp = b.nexp;
+    F.blk.ell = b.ell;
     F.blk.bptr = b.bptr;
     F.blk.brows = b.brows;
     F.blk.iptr = b.iptr;
@@ -987,6 +988,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
     F.blk.nexp = b.nexp;
+    F.blk.ell = b.ell;
     F.blk.bptr = b.bptr;
     F.blk.brows = b.brows;
     F.blk.iptr = b.iptr;
