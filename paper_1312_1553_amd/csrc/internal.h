@@ -12,7 +12,10 @@ constexpr int kMaxP = 32;      // eigenpairs per solve
 constexpr int kMaxK = 16;      // BFGS window
 constexpr int kMaxQ = kMaxP + 1;
 constexpr int kMaxVec = 80;    // vectors in one kernel argument list
-constexpr int kNBMax = 2048;   // blocks of a streaming kernel (partials per dot)
+#ifndef BNX_NBMAX
+#define BNX_NBMAX 2048
+#endif
+constexpr int kNBMax = BNX_NBMAX;  // blocks of a streaming kernel (partials per dot)
 constexpr int kPartSlots = 80; // dots per partial area
 constexpr int kAreas = 10;     // partial areas
 constexpr int kBlock = 256;

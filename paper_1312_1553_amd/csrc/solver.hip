@@ -82,6 +82,13 @@ __device__ void reduce_parts(const double *part, int nb, int D, double *out) {
   __syncthreads();
 }
 
+// Convergence flag of an iteration, written straight into pinned host memory (the host polls it after the
+// iteration's event instead of copying it).
+__device__ void post_flag(int *hflag, int v) {
+  __hip_atomic_store(hflag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+}
+
 template <typename T, int MAXD>
 __device__ __forceinline__ void bpart(T (&acc)[MAXD], int nd, double *part) {
   __shared__ double red[4][MAXD];
@@ -328,8 +335,13 @@ __global__ void c_pcg_q(DevCtl *c, const double *part, int nb) {
 }
 
 // exit tests (Sec. 4.3) and, when continuing, first-loop coefficients
-__global__ void c_pcg_exit(DevCtl *c, const double *part, int nb) {
-  if (c->done) return;
+// Exit tests of the PCG iteration; posts the done flag of the iteration to the host (also when an earlier
+// step of the iteration already ended the solve).
+__global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag) {
+  if (c->done) {
+    if (threadIdx.x == 0) post_flag(hflag, 1);
+    return;
+  }
   __shared__ double red[1];
   if (c->eigtest) reduce_parts(part, nb, 1, red);
   if (threadIdx.x) return;
@@ -343,8 +355,10 @@ __global__ void c_pcg_exit(DevCtl *c, const double *part, int nb) {
   if (why >= 0) {
     c->done = 1;
     c->reason = why;
+    post_flag(hflag, 1);
     return;
   }
+  post_flag(hflag, 0);
   first_loop(c);
 }
 
@@ -539,18 +553,38 @@ __global__ __launch_bounds__(kBlock) void k_dacg_scale(int n, const DevCtl *c, T
   bpart<T, 2>(acc, 2, part);
 }
 
+// Scale the iterate (x = x' inv, Ax = Ax' inv when inv != 0: the norm of x' comes from the previous step),
+// g = Ax - q x with the scale-invariant q = x'^T A x' / x'^T x'; dot g^T g.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, const T *x, const T *Ax, T *g,
-                                                      double *part) {
+__global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T *x, T *Ax, T *g, double *part) {
   if (c->ddone) return;
+  const T inv = (T)c->dinv;
   const T q = (T)c->dq;
   T acc[1] = {T(0)};
   GRIDLOOP(i, n) {
-    const T gi = Ax[i] - q * x[i];
+    T xi = x[i], ai = Ax[i];
+    if (inv != T(0)) {
+      xi *= inv;
+      ai *= inv;
+      x[i] = xi;
+      Ax[i] = ai;
+    }
+    const T gi = ai - q * xi;
     g[i] = gi;
     acc[0] += gi * gi;
   }
   bpart<T, 1>(acc, 1, part);
+}
+
+// convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host
+__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag) {
+  if (c->ddone) return;
+  __shared__ double red[1];
+  reduce_parts(part, nb, 1, red);
+  if (threadIdx.x) return;
+  c->dgn = sqrt(red[0] / c->dxx);
+  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax) c->ddone = 1;
+  post_flag(hflag, c->ddone);
 }
 
 __global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
@@ -561,15 +595,6 @@ __global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
   c->dxx = red[0];
   c->dxAx = red[1];
   c->dq = red[1] / red[0];
-}
-
-__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb) {
-  if (c->ddone) return;
-  __shared__ double red[1];
-  reduce_parts(part, nb, 1, red);
-  if (threadIdx.x) return;
-  c->dgn = sqrt(red[0] / c->dxx);
-  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax) c->ddone = 1;
 }
 
 // after multi-dot (Qt^T c0 (nq), g^T c0): zQ, gamma, beta
@@ -624,28 +649,35 @@ __global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const dou
   c->dalpha = (q2 < q1) ? r2 : r1;
 }
 
-// x += a d, Ax += a Ad; dots ||x||^2 (for the next scale)
+// x' = x + a d, Ax' = Ax + a Ad; dots x'^T x', x'^T A x'
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dacg_step(int n, const DevCtl *c, T *x, T *Ax, const T *d, const T *Ad,
                                                       double *part) {
   if (c->ddone) return;
   const T a = (T)c->dalpha;
-  T acc[1] = {T(0)};
+  T acc[2] = {T(0), T(0)};
   GRIDLOOP(i, n) {
     const T xi = x[i] + a * d[i];
+    const T ai = Ax[i] + a * Ad[i];
     x[i] = xi;
-    Ax[i] += a * Ad[i];
+    Ax[i] = ai;
     acc[0] += xi * xi;
+    acc[1] += xi * ai;
   }
-  bpart<T, 1>(acc, 1, part);
+  bpart<T, 2>(acc, 2, part);
 }
 
+// next step: inv = 1/||x'||, q, and the dots of the scaled iterate
 __global__ void c_dacg_next(DevCtl *c, const double *part, int nb) {
   if (c->ddone) return;
-  __shared__ double red[1];
-  reduce_parts(part, nb, 1, red);
+  __shared__ double red[2];
+  reduce_parts(part, nb, 2, red);
   if (threadIdx.x) return;
-  c->dinv = 1.0 / sqrt(red[0]);
+  const double inv = 1.0 / sqrt(red[0]);
+  c->dinv = inv;
+  c->dq = red[1] / red[0];
+  c->dxx = red[0] * inv * inv;
+  c->dxAx = red[1] * inv * inv;
   c->dgamma_prev = c->dgamma;
   c->dits++;
 }
@@ -843,7 +875,8 @@ struct bnx_ctx {
   double *part = nullptr;
   int *counter = nullptr;
   int *dflag = nullptr;    // device int scratch
-  int *hflag = nullptr;    // pinned
+  int *hflag = nullptr;    // pinned, mapped
+  int *dhflag = nullptr;   // device address of hflag
   bool factored = false, solved = false;
   double shift_used = 0.0, t_factor = 0.0;
   int trsv_mode = 0, sf_waves = 0;  // 0: window from the level sizes
@@ -1091,6 +1124,9 @@ void free_work(bnx_ctx *C, Work<T> &w) {
 
 // ------------------------------------------------------------------ lagged done-flag polling
 // The host enqueues iteration l+1 before reading the flag written by iteration l.
+// Lagged host polling of a device convergence flag: the last control step of iteration l writes the flag
+// into pinned host memory (slot l mod 2) and an event follows the iteration; the host reads iteration
+// l-1's flag while iteration l is queued.
 struct Poll {
   bnx_ctx *C;
   hipEvent_t ev[2];
@@ -1098,21 +1134,22 @@ struct Poll {
   explicit Poll(bnx_ctx *c) : C(c) {
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    C->hflag[0] = C->hflag[1] = 0;
   }
   ~Poll() {
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
   }
-  void post(const int *dflag_src) {
-    HIPCHK(hipMemcpyAsync(C->hflag + slot, dflag_src, sizeof(int), hipMemcpyDeviceToHost, C->st));
+  int *flag() const { return C->dhflag + slot; }  // where the current iteration posts its flag
+  void post() {
     HIPCHK(hipEventRecord(ev[slot], C->st));
     slot ^= 1;
   }
-  // read the flag posted before the last post
+  // the flag posted before the last post
   int read_prev() {
-    const int s = slot;  // the older of the two slots
+    const int s = slot;
     HIPCHK(hipEventSynchronize(ev[s]));
-    return C->hflag[s];
+    return __atomic_load_n(&C->hflag[s], __ATOMIC_ACQUIRE);
   }
 };
 
@@ -1194,8 +1231,8 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
                          Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
     hipLaunchKernelGGL(c_pcg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
     hipLaunchKernelGGL((k_pcg_eigres<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, s_out, t, area(L, 2));
-    hipLaunchKernelGGL(c_pcg_exit, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbi);
-    poll.post(gate);
+    hipLaunchKernelGGL(c_pcg_exit, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbi, poll.flag());
+    poll.post();
     if (l > 0 && poll.read_prev()) break;
   }
   DevCtl h = C->readctl();
@@ -1275,13 +1312,14 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   lx.p[0] = w.Ax;
   lx.p[1] = w.x;
   lx.p[2] = w.d;
+  // dots of the starting vector (no scaling: inv = 0)
+  hipLaunchKernelGGL((k_dacg_scale<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, area(L, 0));
+  hipLaunchKernelGGL(c_dacg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbi);
   Poll poll(C);
   int it;
   for (it = 0; it <= itmax; it++) {
-    hipLaunchKernelGGL((k_dacg_scale<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, area(L, 0));
-    hipLaunchKernelGGL(c_dacg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbi);
     hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
-    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
+    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag());
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
@@ -1298,7 +1336,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs, area(L, 9), nbc);
     hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, area(L, 5));
     hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
-    poll.post(gate);
+    poll.post();
     if (it > 0 && poll.read_prev()) break;
   }
   DevCtl h = C->readctl();
@@ -2183,9 +2221,11 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
     }
     C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
+    HIPCHK(hipMemsetAsync(C->counter, 0, 4 * sizeof(int), C->st));
     C->dflag = C->alloc<int>(4);
     HIPCHK(hipHostMalloc((void **)&C->hctl, sizeof(DevCtl), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void **)&C->hflag, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&C->hflag, 4 * sizeof(int), hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer((void **)&C->dhflag, C->hflag, 0));
     HIPCHK(hipMemsetAsync(C->ctl, 0, sizeof(DevCtl), C->st));
     HIPCHK(hipMemcpyAsync(C->rp, C->an.rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
     HIPCHK(hipMemcpyAsync(C->ci, C->an.ci.data(), sizeof(int) * nnz, hipMemcpyHostToDevice, C->st));
