@@ -113,6 +113,8 @@ def main():
                     help="time only the hot kernels at full size (IC solves, SpMV) and a plain copy of known size; "
                          "used under rocprofv3 for the kernel summaries and HBM counters")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--newton", type=int, default=1,
+                    help="1: DACG-Newton (the method); 0: DACG alone to the same tolerance (the paper's DACG rows)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -151,7 +153,7 @@ def main():
     for name, prec in (("mixed", bnx.MIXED), ("fp64", bnx.FP64)):
         for w in range(args.warmup):
             S.factor()
-            ev, V, st = S.solve(p, precision=prec, x0=x0d)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
             print(f"[bench] warmup {name} {w}: {st['t_dacg'] + st['t_newton']:.3f}s status {st['status']}",
                   flush=True)
         bnx.bnx_set_profiling(S.h, 1)
@@ -160,7 +162,7 @@ def main():
         stats = []
         for k in range(args.steps):
             S.factor()
-            ev, V, st = S.solve(p, precision=prec, x0=x0d)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
             stats.append(st)
             print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
                   flush=True)
@@ -236,7 +238,8 @@ def main():
         "dtype": "f32 inner / f64 outer (mixed); fp64 path reported beside it",
         "data": "synthetic",
         "config": {"workload": f"diffusion3d_{N}^3_lognormal_seed1", "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
-                   "parallelism": "single GPU", "trsv_mode": args.trsv_mode},
+                   "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
+                   "method": "DACG-Newton" if args.newton else "DACG alone"},
         "fp64": {"value": round(fp64["eps"], 4), "ms_per_step": round(fp64["ms"], 2), "max_relres": fp64["relres"],
                  "pcg_its": sum(fp64["stats"]["pcg_its"]), "outer_its": sum(fp64["stats"]["outer_its"]),
                  "dacg_its": sum(fp64["stats"]["dacg_its"])},

@@ -70,6 +70,10 @@ typedef struct {
     uint64_t seed;      /* starting block when x0 == NULL: splitmix64 counter generator   (0) */
     const double *x0;   /* optional n x p starting block (host or device per create); NULL = seeded */
     int keep_bfgs;      /* reserved; the backward pass always recomputes its own history  (0) */
+    int newton;         /* 1: DACG-Newton (Alg. 2); 0: DACG alone to tol, the DACG rows of
+                           Tables 4, 5, 7 and 8; it runs in double in both precision modes
+                           (tol is far below the float residual floor); no PCG, outer_its
+                           and pcg_its stay 0                                           (1) */
 } bnx_solve_opts;
 
 /* IC(0) breakdown policy (Sec. 2 initial preconditioner): on a non-positive pivot

@@ -50,6 +50,7 @@
 typedef struct {
     int p, itmax, itmax_dacg, itmax_pcg, kmax, exit_rule;
     double tol, tol_dacg, tol_pcg, exit_xi, shift0, shift_max;
+    int newton; /* 1: DACG-Newton (Alg. 2); 0: DACG alone to tol, the DACG rows of Tables 4, 5, 7 and 8 */
 } or_opts;
 
 typedef struct {
@@ -436,8 +437,9 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
     for (int j = 0; j < p; j++) {
         double *u = Qm + (size_t)j * N; /* becomes v_{j+1} */
         double td = now_s();
-        st->dacg_its[j] = or_dacg(&P, j, Qm, x0 + (size_t)j * N, o->tol_dacg, o->itmax_dacg, u, NULL, 0,
-                                  &st->mvp_dacg, work);
+        /* DACG to tau_DACG before Newton, or to the final tau when it runs alone */
+        st->dacg_its[j] = or_dacg(&P, j, Qm, x0 + (size_t)j * N, o->newton ? o->tol_dacg : o->tol, o->itmax_dacg, u,
+                                  NULL, 0, &st->mvp_dacg, work);
         st->t_dacg += now_s() - td;
 
         double tn = now_s();
@@ -448,7 +450,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
         for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
         double rn = nrm2(n, r);
         int k = 0, slow = 0, restarts = 0;
-        while (rn > o->tol * theta && k < o->itmax) {
+        while (o->newton && rn > o->tol * theta && k < o->itmax) {
             int its = 0;
             int why = or_pcg(&P, theta, j + 1, Qm, u, Au, r, W.k, W.S, W.R, W.alpha, o->tol_pcg, o->itmax_pcg,
                              o->tol, o->exit_rule, o->exit_xi, s, &its, work);

@@ -1432,9 +1432,22 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     cgs2_normalize(C, x64, tmp, j, Qt64);
     launch_cast<double, T>(C->st, n, x64, w.x);
     long long mvp = 0;
-    S.dacg_its[j] = dacg<T>(C, w, j, QtT, o.tol_dacg, o.itmax_dacg, &mvp);
+    // DACG to tau_DACG before Newton; alone, to the final tau, and then always in double (tau is far
+    // below the float residual floor)
+    const bool alone = o.newton == 0;
+    if (alone && !fp64) {
+      if (!w64) {
+        w64.reset(new Work<double>);
+        make_work<double>(C, *w64, 0, 0);
+      }
+      HIPCHK(hipMemcpyAsync(w64->x, x64, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+      S.dacg_its[j] = dacg<double>(C, *w64, j, Qt64, o.tol, o.itmax_dacg, &mvp);
+      HIPCHK(hipMemcpyAsync(u, w64->x, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+    } else {
+      S.dacg_its[j] = dacg<T>(C, w, j, QtT, alone ? o.tol : o.tol_dacg, o.itmax_dacg, &mvp);
+      launch_cast<T, double>(C->st, n, w.x, u);
+    }
     S.mvp_dacg += mvp;
-    launch_cast<T, double>(C->st, n, w.x, u);
     C->sync();
     S.t_dacg += now_s() - t0;
 
@@ -1449,7 +1462,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     double theta = h.otheta, rn = h.orn;
     std::deque<int> ring;  // chronological slots
     int k = 0, slow = 0, restarts = 0;
-    while (rn > o.tol * theta && k < o.itmax) {
+    while (!alone && rn > o.tol * theta && k < o.itmax) {
       const int m = j + 1;
       VList<T> Q = QtT;
       Q.p[j] = uT;
@@ -2070,6 +2083,7 @@ void bnx_default_solve_opts(bnx_solve_opts *o) {
   o->seed = 0;
   o->x0 = nullptr;
   o->keep_bfgs = 0;
+  o->newton = 1;
 }
 
 void bnx_default_factor_opts(bnx_factor_opts *o) {

@@ -368,3 +368,24 @@ def test_latency_probe():
     with pytest.raises(bnx.BnxError):
         bnx.bnx_probe_latency(S.h, 0, 1)
     S.close()
+
+
+@pytest.mark.parametrize("name,p", [("laplace2d_32", 4), ("diffusion_12", 6), ("elasticity_3", 4)])
+def test_pure_dacg_matches_oracle(oracle_mod, name, p):
+    """DACG alone to tau (newton = 0; it runs in double in both precision modes): eigenvalues against the
+    oracle's, residuals, and the DACG iteration count of every pair within 2 of the oracle's."""
+    A = mats()[name]
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0, newton=0)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case pure dacg", name, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, newton=0)
+        ev = ev.numpy()
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, host(V), 1e-8)
+        assert st["status"] == 0 and sum(st["pcg_its"]) == 0 and sum(st["outer_its"]) == 0
+        for a, b in zip(sorted(st["dacg_its"]), sorted(st_o["dacg_its"])):
+            assert abs(a - b) <= 2, (st["dacg_its"], st_o["dacg_its"])
+    S.close()

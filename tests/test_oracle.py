@@ -450,3 +450,22 @@ def test_backward_matches_finite_differences(oracle_lib):
         d = rng.standard_normal(len(logk))
         fd = (loss(logk + h * d)[0] - loss(logk - h * d)[0]) / (2 * h)
         assert abs(fd - grad @ d) <= 1e-6 * abs(fd) + 1e-9
+
+
+def test_pure_dacg_closed_form_and_dense(oracle_lib):
+    """DACG alone to tau (the DACG rows of Tables 4, 5, 7, 8): closed-form 2-D Laplacian eigenvalues, dense
+    eigh on a heterogeneous 8^3 diffusion matrix, no Newton or PCG work, residual <= tau per pair."""
+    A, p = W.config_small()
+    ev, Vr, st, _ = oracle_lib.solve(A, p, x0=W.initial_block(A.n, p, 0), newton=0)
+    np.testing.assert_allclose(ev, W.laplacian_2d_eigs(32)[:p], rtol=1e-10)
+    _check_pairs(A, ev, Vr)
+    assert st["status"] == 0 and sum(st["pcg_its"]) == 0 and sum(st["outer_its"]) == 0
+    assert st["mvp_newton"] == p  # the closing residual evaluation of each pair only
+    B = W.diffusion_3d(8, seed=1)
+    ev2, V2, st2, _ = oracle_lib.solve(B, 5, newton=0)
+    np.testing.assert_allclose(ev2, np.linalg.eigvalsh(dense(B))[:5], rtol=1e-10)
+    _check_pairs(B, ev2, V2)
+    # same eigenpairs as DACG-Newton; DACG alone needs more DACG steps than the tau_DACG phase of DACG-Newton
+    ev3, _, st3, _ = oracle_lib.solve(B, 5)
+    np.testing.assert_allclose(ev2, ev3, rtol=1e-10)
+    assert sum(st2["dacg_its"]) > sum(st3["dacg_its"])
