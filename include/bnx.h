@@ -74,6 +74,9 @@ typedef struct {
                            Tables 4, 5, 7 and 8; it runs in double in both precision modes
                            (tol is far below the float residual floor); no PCG, outer_its
                            and pcg_its stay 0                                           (1) */
+    int bfgs_full;      /* 0: pairs (s_k, r_k) of the simplified update eq. (2.2), y_k ~ -r_k;
+                           1: y_k = r_{k+1} - r_k of eq. (2.1), stored as (s_k, r_k - r_{k+1}) and
+                           skipped unless s_k^T y_k > 0                                  (0) */
 } bnx_solve_opts;
 
 /* IC(0) breakdown policy (Sec. 2 initial preconditioner): on a non-positive pivot

@@ -31,7 +31,7 @@ class Opts(C.Structure):
     _fields_ = [("p", C.c_int), ("itmax", C.c_int), ("itmax_dacg", C.c_int), ("itmax_pcg", C.c_int),
                 ("kmax", C.c_int), ("exit_rule", C.c_int), ("tol", C.c_double), ("tol_dacg", C.c_double),
                 ("tol_pcg", C.c_double), ("exit_xi", C.c_double), ("shift0", C.c_double),
-                ("shift_max", C.c_double), ("newton", C.c_int)]
+                ("shift_max", C.c_double), ("newton", C.c_int), ("bfgs_full", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -102,9 +102,10 @@ NULLD = C.cast(None, _pd)
 def default_opts(p: int, **kw) -> Opts:
     """Defaults of the paper's parameter table (tau 1e-8, IMAX 100, tau_DACG 1e-2,
     tau_PCG 1e-2, IMAX_PCG 20) with k_max = 5 and the floor exit rule (xi = 0.1).
-    newton=0 runs DACG alone to tau (the DACG rows of Tables 4, 5, 7 and 8)."""
+    newton=0 runs DACG alone to tau (the DACG rows of Tables 4, 5, 7 and 8); bfgs_full=1 stores the
+    pairs of eq. (2.1) with y_k = r_{k+1} - r_k instead of the simplified y_k ~ -r_k of eq. (2.2)."""
     d = dict(p=p, itmax=100, itmax_dacg=5000, itmax_pcg=20, kmax=5, exit_rule=1, tol=1e-8, tol_dacg=1e-2,
-             tol_pcg=1e-2, exit_xi=0.1, shift0=1e-3, shift_max=1.0, newton=1)
+             tol_pcg=1e-2, exit_xi=0.1, shift0=1e-3, shift_max=1.0, newton=1, bfgs_full=0)
     d.update(kw)
     return Opts(**d)
 

@@ -51,6 +51,8 @@ typedef struct {
     int p, itmax, itmax_dacg, itmax_pcg, kmax, exit_rule;
     double tol, tol_dacg, tol_pcg, exit_xi, shift0, shift_max;
     int newton; /* 1: DACG-Newton (Alg. 2); 0: DACG alone to tol, the DACG rows of Tables 4, 5, 7 and 8 */
+    int bfgs_full; /* 0: pairs (s_k, r_k) of eq. (2.2), y_k ~ -r_k; 1: y_k = r_{k+1} - r_k of eq. (2.1), stored
+                      as (s_k, r_k - r_{k+1}) so that Alg. 1 applies unchanged */
 } or_opts;
 
 typedef struct {
@@ -428,6 +430,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
     double *Au = malloc(sizeof(double) * N), *r = malloc(sizeof(double) * N), *s = malloc(sizeof(double) * N);
     double *work = malloc(sizeof(double) * N * 9);
     double *xn = malloc(sizeof(double) * N);
+    double *yk = malloc(sizeof(double) * N);
     pairs_t W = {0, o->kmax, n, malloc(sizeof(double) * N * (o->kmax > 0 ? o->kmax : 1)),
                  malloc(sizeof(double) * N * (o->kmax > 0 ? o->kmax : 1)), {0}};
     double lam[OR_MAXP];
@@ -466,14 +469,26 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
             cgs(n, j, Qm, xn, z);
             scal(n, 1.0 / nrm2(n, xn), xn);
             /* store the pair (s_k, r_k) (Alg. 2) unless it would break positive definiteness */
-            if (alpha < -1e-12 * sqrt(sn2) * rn) pairs_push(&W, s, r, alpha);
-            else st->bfgs_skipped++;
+            if (!o->bfgs_full) {
+                if (alpha < -1e-12 * sqrt(sn2) * rn) pairs_push(&W, s, r, alpha);
+                else st->bfgs_skipped++;
+            } else {
+                copy(n, r, yk); /* r_k, kept for y_k once r_{k+1} is known */
+            }
             copy(n, xn, u);
             or_spmv(n, rp, ci, v, u, Au);
             st->mvp_newton++;
             double theta1 = dot(n, u, Au);
             for (int i = 0; i < n; i++) r[i] = Au[i] - theta1 * u[i];
             double rn1 = nrm2(n, r);
+            if (o->bfgs_full) {
+                /* eq. (2.1) with y_k = r_{k+1} - r_k: the stored vector is -y_k = r_k - r_{k+1} and
+                   alpha = s^T(-y_k) < 0 is the curvature condition s^T y > 0 */
+                for (int i = 0; i < n; i++) yk[i] -= r[i];
+                double ay = dot(n, s, yk);
+                if (ay < -1e-12 * sqrt(sn2) * nrm2(n, yk)) pairs_push(&W, s, yk, ay);
+                else st->bfgs_skipped++;
+            }
             if (trace && st->ntrace < trace_cap) {
                 double *T = trace + 8 * (size_t)st->ntrace++;
                 T[0] = j; T[1] = k; T[2] = theta; T[3] = rn; T[4] = alpha; T[5] = sn2; T[6] = theta1; T[7] = its;
@@ -529,7 +544,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
         for (int i = 0; i < n; i++) out[i] = sg * u[i];
         evals[j] = lam[idx[j]];
     }
-    free(P.tmp); free(Qm); free(Au); free(r); free(s); free(work); free(xn); free(W.S); free(W.R);
+    free(P.tmp); free(Qm); free(Au); free(r); free(s); free(work); free(xn); free(yk); free(W.S); free(W.R);
     free(Lrp); free(Lci); free(Lv);
     st->status = allconv ? 0 : 1;
     return st->status;

@@ -43,6 +43,7 @@ struct DevCtl {
   int dits, ddone, ditmax;
   // outer step (always double)
   double oz[kMaxQ], onrm2, otheta, orn, oalpha, osn2, ornold;
+  double oya, oyn2;  // s^T (r_k - r_{k+1}) and ||r_k - r_{k+1}||^2 for the full BFGS pair
   // backward
   double bz[kMaxQ];
   int err;  // bounded wait exceeded somewhere

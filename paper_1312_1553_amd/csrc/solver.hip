@@ -503,6 +503,20 @@ __global__ void c_gram(DevCtl *c, const double *part, int nb, int shift, int ins
   for (int t = 0; t < k; t++) c->QS[nqt * kMaxK + t] = red[o + t];
 }
 
+// out = r_k - r_{k+1} (the stored vector of the full BFGS pair, eq. (2.1) with y_k = r_{k+1} - r_k)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ydiff(int n, const double *rk, const double *rk1, T *out) {
+  GRIDLOOP(i, n) out[i] = (T)(rk[i] - rk1[i]);
+}
+
+__global__ void c_outer_y(DevCtl *c, const double *part, int nb) {
+  __shared__ double red[2];
+  reduce_parts(part, nb, 2, red);
+  if (threadIdx.x) return;
+  c->oya = red[0];
+  c->oyn2 = red[1];
+}
+
 // Gram blocks from scratch, rows row0..row0+nrows-1 of M (kind 0, s_s^T r_t) or of Q^T S (kind 1)
 __global__ void c_gram_rows(DevCtl *c, const double *part, int nb, int k, int kind, int row0, int nrows) {
   __shared__ double red[kPartSlots];
@@ -1507,8 +1521,24 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
       S.mvp_newton++;
       h = C->readctl();
       const double alpha = h.oalpha, sn2 = h.osn2;
-      // ---- store the pair (s_k, r_k) in the k_max window (Sec. 4.4)
-      const bool insert = o.kmax > 0 && alpha < -1e-12 * std::sqrt(sn2) * rn;
+      // ---- store the pair in the k_max window (Sec. 4.4): (s_k, r_k), or with the full update of eq. (2.1)
+      //      (s_k, r_k - r_{k+1}); either way alpha = s^T(stored) < 0 keeps the preconditioner SPD
+      bool insert;
+      if (o.bfgs_full) {
+        const int nbi2 = gridn(n);
+        hipLaunchKernelGGL((k_ydiff<T>), dim3(nbi2), dim3(kBlock), 0, C->st, n, r_old, r_new, w.z);
+        VList<T> X{}, Y{};
+        X.p[0] = w.s;
+        Y.p[0] = w.z;
+        X.p[1] = w.z;
+        Y.p[1] = w.z;
+        const int nb2 = launch_multidot<T, double>(L, n, 2, X, Y, area(L, 4), nullptr);
+        hipLaunchKernelGGL(c_outer_y, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb2);
+        const DevCtl hy = C->readctl();
+        insert = o.kmax > 0 && hy.oya < -1e-12 * std::sqrt(sn2) * std::sqrt(hy.oyn2);
+      } else {
+        insert = o.kmax > 0 && alpha < -1e-12 * std::sqrt(sn2) * rn;
+      }
       int shift = 0;
       if (insert) {
         int slot;
@@ -1528,7 +1558,8 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
             }
         }
         HIPCHK(hipMemcpyAsync(w.S[slot], w.s, sizeof(T) * n, hipMemcpyDeviceToDevice, C->st));
-        launch_cast<double, T>(C->st, n, r_old, w.R[slot]);
+        if (o.bfgs_full) HIPCHK(hipMemcpyAsync(w.R[slot], w.z, sizeof(T) * n, hipMemcpyDeviceToDevice, C->st));
+        else launch_cast<double, T>(C->st, n, r_old, w.R[slot]);
         ring.push_back(slot);
       } else {
         S.bfgs_skipped++;
@@ -2084,6 +2115,7 @@ void bnx_default_solve_opts(bnx_solve_opts *o) {
   o->x0 = nullptr;
   o->keep_bfgs = 0;
   o->newton = 1;
+  o->bfgs_full = 0;
 }
 
 void bnx_default_factor_opts(bnx_factor_opts *o) {

@@ -48,9 +48,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "bnx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(bnx_solve_opts), offsetof(bnx_solve_opts, seed),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(bnx_solve_opts), offsetof(bnx_solve_opts, seed),
          offsetof(bnx_solve_opts, x0), offsetof(bnx_solve_opts, keep_bfgs), offsetof(bnx_solve_opts, newton),
-         sizeof(bnx_stats), offsetof(bnx_stats, mvp_dacg), offsetof(bnx_stats, t_newton));
+         offsetof(bnx_solve_opts, bfgs_full), sizeof(bnx_stats), offsetof(bnx_stats, mvp_dacg),
+         offsetof(bnx_stats, t_newton));
   printf("%zu\n", sizeof(bnx_factor_opts));
   return 0;
 }
@@ -63,8 +64,8 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split()
     got = [int(x) for x in out]
     S, T = bnx.SolveOpts, bnx.Stats
-    want = [ctypes.sizeof(S), S.seed.offset, S.x0.offset, S.keep_bfgs.offset, S.newton.offset, ctypes.sizeof(T),
-            T.mvp_dacg.offset, T.t_newton.offset, ctypes.sizeof(bnx.FactorOpts)]
+    want = [ctypes.sizeof(S), S.seed.offset, S.x0.offset, S.keep_bfgs.offset, S.newton.offset, S.bfgs_full.offset,
+            ctypes.sizeof(T), T.mvp_dacg.offset, T.t_newton.offset, ctypes.sizeof(bnx.FactorOpts)]
     assert got == want
 
 

@@ -389,3 +389,24 @@ def test_pure_dacg_matches_oracle(oracle_mod, name, p):
         for a, b in zip(sorted(st["dacg_its"]), sorted(st_o["dacg_its"])):
             assert abs(a - b) <= 2, (st["dacg_its"], st_o["dacg_its"])
     S.close()
+
+
+@pytest.mark.parametrize("name,p,kw", [("diffusion_12", 6, {}), ("diffusion_40", 3, {"itmax_pcg": 5, "tol_pcg": 1e-4})])
+def test_full_bfgs_matches_oracle(oracle_mod, name, p, kw):
+    """bfgs_full = 1 (eq. (2.1), y_k = r_{k+1} - r_k) against the oracle: eigenvalues, residuals, and the
+    fp64 PCG iteration total within 10 %."""
+    A = mats()[name]
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0, bfgs_full=1, **kw)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case full bfgs", name, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, bfgs_full=1, **kw)
+        ev = ev.numpy()
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, host(V), 1e-8)
+        assert st["status"] == 0
+        if prec == FP64:
+            assert abs(sum(st["pcg_its"]) - sum(st_o["pcg_its"])) <= 0.1 * sum(st_o["pcg_its"]) + 2
+    S.close()

@@ -469,3 +469,21 @@ def test_pure_dacg_closed_form_and_dense(oracle_lib):
     ev3, _, st3, _ = oracle_lib.solve(B, 5)
     np.testing.assert_allclose(ev2, ev3, rtol=1e-10)
     assert sum(st2["dacg_its"]) > sum(st3["dacg_its"])
+
+
+def test_full_bfgs_pairs(oracle_lib):
+    """The full update of eq. (2.1) (y_k = r_{k+1} - r_k): closed-form and dense eigenvalues, the same
+    eigenpairs as the simplified update, and a different Newton history once pairs accumulate (small
+    IMAX_PCG forces several outer steps per pair)."""
+    A, p = W.config_small()
+    ev, Vr, st, _ = oracle_lib.solve(A, p, x0=W.initial_block(A.n, p, 0), bfgs_full=1)
+    np.testing.assert_allclose(ev, W.laplacian_2d_eigs(32)[:p], rtol=1e-10)
+    _check_pairs(A, ev, Vr)
+    B = W.diffusion_3d(20, seed=1)
+    kw = dict(itmax_pcg=5, tol_pcg=1e-4)
+    ev1, V1, st1, _ = oracle_lib.solve(B, 4, bfgs_full=1, **kw)
+    ev0, V0, st0, _ = oracle_lib.solve(B, 4, bfgs_full=0, **kw)
+    _check_pairs(B, ev1, V1)
+    np.testing.assert_allclose(ev1, ev0, rtol=1e-10)
+    assert st1["pcg_its"] != st0["pcg_its"]
+    assert st1["status"] == 0
