@@ -31,7 +31,8 @@ class Opts(C.Structure):
     _fields_ = [("p", C.c_int), ("itmax", C.c_int), ("itmax_dacg", C.c_int), ("itmax_pcg", C.c_int),
                 ("kmax", C.c_int), ("exit_rule", C.c_int), ("tol", C.c_double), ("tol_dacg", C.c_double),
                 ("tol_pcg", C.c_double), ("exit_xi", C.c_double), ("shift0", C.c_double),
-                ("shift_max", C.c_double), ("newton", C.c_int), ("bfgs_full", C.c_int)]
+                ("shift_max", C.c_double), ("newton", C.c_int), ("bfgs_full", C.c_int), ("ict", C.c_int),
+                ("lfil", C.c_int), ("tau_ic", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -39,7 +40,8 @@ class Stats(C.Structure):
                 ("converged", C.c_int * MAXP), ("relres", C.c_double * MAXP), ("mvp_dacg", C.c_longlong),
                 ("mvp_newton", C.c_longlong), ("bfgs_skipped", C.c_int), ("pcg_breakdowns", C.c_int),
                 ("ntrace", C.c_int), ("status", C.c_int), ("shift_used", C.c_double), ("t_factor", C.c_double),
-                ("t_dacg", C.c_double), ("t_newton", C.c_double), ("dacg_restarts", C.c_int)]
+                ("t_dacg", C.c_double), ("t_newton", C.c_double), ("dacg_restarts", C.c_int),
+                ("nnz_L", C.c_longlong), ("fill", C.c_double)]
 
     def as_dict(self, p: int) -> dict:
         return {
@@ -49,6 +51,7 @@ class Stats(C.Structure):
             "bfgs_skipped": self.bfgs_skipped, "pcg_breakdowns": self.pcg_breakdowns,
             "status": self.status, "shift_used": self.shift_used, "t_factor": self.t_factor,
             "t_dacg": self.t_dacg, "t_newton": self.t_newton, "dacg_restarts": self.dacg_restarts,
+            "nnz_L": self.nnz_L, "fill": self.fill,
         }
 
 
@@ -67,6 +70,13 @@ def lib():
         L.or_tril_nnz.restype = C.c_int
         L.or_ic0.argtypes = [C.c_int, _pi, _pi, _pd, C.c_double, C.c_double, _pi, _pi, _pd, _pd]
         L.or_ic0.restype = C.c_int
+        _ppi = C.POINTER(_pi)
+        _ppd = C.POINTER(_pd)
+        L.or_ict.argtypes = [C.c_int, _pi, _pi, _pd, C.c_int, C.c_double, C.c_double, C.c_double, _ppi, _ppi,
+                             _ppd, _pd]
+        L.or_ict.restype = C.c_int
+        L.or_free.argtypes = [C.c_void_p]
+        L.or_free.restype = None
         L.or_lsolve.argtypes = [C.c_int, _pi, _pi, _pd, _pd, _pd]
         L.or_ltsolve.argtypes = [C.c_int, _pi, _pi, _pd, _pd, _pd]
         L.or_linesearch.argtypes = [C.c_double] * 6
@@ -103,9 +113,11 @@ def default_opts(p: int, **kw) -> Opts:
     """Defaults of the paper's parameter table (tau 1e-8, IMAX 100, tau_DACG 1e-2,
     tau_PCG 1e-2, IMAX_PCG 20) with k_max = 5 and the floor exit rule (xi = 0.1).
     newton=0 runs DACG alone to tau (the DACG rows of Tables 4, 5, 7 and 8); bfgs_full=1 stores the
-    pairs of eq. (2.1) with y_k = r_{k+1} - r_k instead of the simplified y_k ~ -r_k of eq. (2.2)."""
+    pairs of eq. (2.1) with y_k = r_{k+1} - r_k instead of the simplified y_k ~ -r_k of eq. (2.2); ict=1
+    preconditions with IC(lfil, tau_ic) (Sec. 2; lfil 30, tau_IC 1e-2 as in Table 2) instead of IC(0)."""
     d = dict(p=p, itmax=100, itmax_dacg=5000, itmax_pcg=20, kmax=5, exit_rule=1, tol=1e-8, tol_dacg=1e-2,
-             tol_pcg=1e-2, exit_xi=0.1, shift0=1e-3, shift_max=1.0, newton=1, bfgs_full=0)
+             tol_pcg=1e-2, exit_xi=0.1, shift0=1e-3, shift_max=1.0, newton=1, bfgs_full=0, ict=0, lfil=30,
+             tau_ic=1e-2)
     d.update(kw)
     return Opts(**d)
 
@@ -118,7 +130,7 @@ def spmv(A, x):
 
 
 class Factor:
-    """IC(0) factor in CSR (rows of L, diagonal last)."""
+    """Incomplete Cholesky factor in CSR (rows of L, diagonal last)."""
 
     def __init__(self, rowptr, col, val, shift):
         self.rowptr, self.col, self.val, self.shift = rowptr, col, val, shift
@@ -141,6 +153,25 @@ def ic0(A, shift0=1e-3, shift_max=1.0) -> Factor:
                       Lv.ctypes.data_as(_pd), C.byref(sh))
     if rc != 0:
         raise RuntimeError(f"IC(0) failed (code {rc})")
+    return Factor(Lrp, Lci, Lv, sh.value)
+
+
+def ict(A, lfil=30, tau=1e-2, shift0=1e-3, shift_max=1.0) -> Factor:
+    """IC(lfil, tau_IC) factor of Sec. 2 (dropping rule at or_ict in oracle.c)."""
+    rp, prp = _i(A.rowptr); ci, pci = _i(A.col); v, pv = _d(A.val)
+    pLrp = _pi(); pLci = _pi(); pLv = _pd()
+    sh = C.c_double(0)
+    rc = lib().or_ict(A.n, prp, pci, pv, int(lfil), float(tau), shift0, shift_max, C.byref(pLrp), C.byref(pLci),
+                      C.byref(pLv), C.byref(sh))
+    if rc != 0:
+        raise RuntimeError(f"IC(lfil, tau) failed (code {rc})")
+    n = A.n
+    Lrp = np.ctypeslib.as_array(pLrp, shape=(n + 1,)).copy()
+    nl = int(Lrp[n])
+    Lci = np.ctypeslib.as_array(pLci, shape=(nl,)).copy()
+    Lv = np.ctypeslib.as_array(pLv, shape=(nl,)).copy()
+    for q in (pLrp, pLci, pLv):
+        lib().or_free(C.cast(q, C.c_void_p))
     return Factor(Lrp, Lci, Lv, sh.value)
 
 

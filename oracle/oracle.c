@@ -31,6 +31,8 @@
  *   the BFGS history restarts with each eigenpair (k := 0 in Alg. 2);
  *   IC(0) on the pattern of tril(A); on a non-positive pivot the factor is
  *   restarted on A + a*diag(A), a = shift0, 2*shift0, ... <= shift_max;
+ *   IC(lfil, tau_IC): ILUT-style dual dropping on the diagonally scaled matrix
+ *   (the rule is spelled out at or_ict);
  *   DACG is a preconditioned Fletcher-Reeves nonlinear CG on the Rayleigh
  *   quotient over the complement of the converged eigenvectors, with an exact
  *   line search (closed-form minimiser of q(x + a d));
@@ -53,6 +55,9 @@ typedef struct {
     int newton; /* 1: DACG-Newton (Alg. 2); 0: DACG alone to tol, the DACG rows of Tables 4, 5, 7 and 8 */
     int bfgs_full; /* 0: pairs (s_k, r_k) of eq. (2.2), y_k ~ -r_k; 1: y_k = r_{k+1} - r_k of eq. (2.1), stored
                       as (s_k, r_k - r_{k+1}) so that Alg. 1 applies unchanged */
+    int ict;       /* 0: IC(0) on the pattern of tril(A); 1: IC(lfil, tau_ic) of Sec. 2 (or_ict) */
+    int lfil;
+    double tau_ic;
 } or_opts;
 
 typedef struct {
@@ -62,6 +67,8 @@ typedef struct {
     int bfgs_skipped, pcg_breakdowns, ntrace, status;
     double shift_used, t_factor, t_dacg, t_newton;
     int dacg_restarts;
+    long long nnz_L; /* entries of the factor L, diagonal included */
+    double fill;     /* sigma of Sec. 5: nnz(L) / nnz(tril(A)) */
 } or_stats;
 
 static double now_s(void) {
@@ -159,6 +166,173 @@ int or_ic0(int n, const int *rp, const int *ci, const double *v, double shift0, 
     }
     if (shift_used) *shift_used = a;
     return 0;
+}
+
+/*
+ * IC(lfil, tau_IC) factor, Sec. 2: the paper's own initial preconditioner, an
+ * incomplete Cholesky factor with at most lfil entries off the diagonal in each
+ * row of L and small entries dropped below the threshold tau_IC.  The paper
+ * names only the two parameters; the dual dropping rule taken here follows
+ * ILUT, row by row:
+ *   the factor Ls is computed for the diagonally scaled matrix As = D^-1/2 A D^-1/2
+ *   (D = diag(A), As_ij = (a_ij r_i) r_j with r_i = 1/sqrt(a_ii), diagonal included),
+ *   so that the drop rule does not depend on the scaling of A, and returned as
+ *   L = D^1/2 Ls (row i of Ls times sqrt(a_ii));
+ *   row i: tau_i = tau_IC ||As(i,:)||_2 (the whole row, summed in column order);
+ *   w = strictly lower part of row i of As; for k ascending over the nonzeros of
+ *   w, fill included: l = w_k / Ls_kk; if |l| < tau_i the entry is dropped and
+ *   takes no part in the elimination, else it is a candidate Ls_ik = l and
+ *   w_m -= l Ls_mk for every earlier row m > k holding an entry in column k
+ *   (which may create fill at m);
+ *   of the candidates the lfil largest in magnitude are kept (ties go to the
+ *   smaller column); Ls_ii = sqrt(As_ii - sum of the kept Ls_ik^2 in column order);
+ *   a pivot <= 0 restarts the whole factorisation, scaling and thresholds
+ *   included, on A + a diag(A) (diagonal a_ii (1 + a)), a = shift0, 2 shift0, ...
+ *   <= shift_max.
+ * With tau_IC = 0 and lfil >= n - 1 this is the exact Cholesky factor.
+ * Output: CSR of L (columns ascending, diagonal last) in arrays allocated here
+ * (release each with or_free).  Returns 0, -1 when no shift up to shift_max
+ * gives positive pivots, -2 for a missing or non-positive diagonal or lfil < 0.
+ */
+typedef struct { int col; double val; } ict_ent;
+
+static int ict_by_size(const void *a, const void *b) {
+    const ict_ent *x = a, *y = b;
+    double ax = fabs(x->val), ay = fabs(y->val);
+    if (ax != ay) return ax > ay ? -1 : 1;
+    return x->col - y->col;
+}
+
+static int ict_by_col(const void *a, const void *b) {
+    return ((const ict_ent *)a)->col - ((const ict_ent *)b)->col;
+}
+
+void or_free(void *p) { free(p); }
+
+int or_ict(int n, const int *rp, const int *ci, const double *v, int lfil, double tau, double shift0,
+           double shift_max, int **Lrp_out, int **Lci_out, double **Lv_out, double *shift_used) {
+    size_t N = (size_t)n;
+    if (lfil < 0) return -2;
+    double *dg = malloc(sizeof(double) * N);
+    for (int i = 0; i < n; i++) {
+        dg[i] = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; e++)
+            if (ci[e] == i) dg[i] = v[e];
+        if (!(dg[i] > 0.0)) { free(dg); return -2; }
+    }
+    double *r = malloc(sizeof(double) * N), *sq = malloc(sizeof(double) * N), *taui = malloc(sizeof(double) * N);
+    double *ds = malloc(sizeof(double) * N); /* diagonal of As */
+    double *w = calloc(N, sizeof(double));
+    int *inw = malloc(sizeof(int) * N);   /* position m holds a pending entry of the current row */
+    int *list = malloc(sizeof(int) * N);  /* pending positions of the current row, ascending */
+    ict_ent *cand = malloc(sizeof(ict_ent) * N);
+    int *head = malloc(sizeof(int) * N), *tail = malloc(sizeof(int) * N); /* column lists of Ls */
+    size_t cap = (size_t)rp[n] + N;
+    int *Lrp = malloc(sizeof(int) * (N + 1));
+    int *Lci = malloc(sizeof(int) * cap), *Lrow = malloc(sizeof(int) * cap), *nxt = malloc(sizeof(int) * cap);
+    double *Lv = malloc(sizeof(double) * cap);
+    double a = 0.0;
+    int rc = 0;
+    for (;;) {
+        /* scaling of the matrix factored in this attempt, A + a diag(A) */
+        for (int i = 0; i < n; i++) {
+            double d = dg[i] * (1.0 + a);
+            sq[i] = sqrt(d);
+            r[i] = 1.0 / sq[i];
+            ds[i] = d * r[i] * r[i];
+        }
+        for (int i = 0; i < n; i++) {
+            double s2 = 0.0;
+            for (int e = rp[i]; e < rp[i + 1]; e++) {
+                double as = ci[e] == i ? ds[i] : v[e] * r[i] * r[ci[e]];
+                s2 += as * as;
+            }
+            taui[i] = tau * sqrt(s2);
+        }
+        for (int i = 0; i < n; i++) { inw[i] = 0; head[i] = tail[i] = -1; }
+        size_t nz = 0;
+        int ok = 1;
+        Lrp[0] = 0;
+        for (int i = 0; i < n && ok; i++) {
+            int len = 0;
+            for (int e = rp[i]; e < rp[i + 1]; e++) {
+                int j = ci[e];
+                if (j >= i) continue;
+                w[j] = v[e] * r[i] * r[j];
+                inw[j] = 1;
+                list[len++] = j; /* the columns of a CSR row ascend */
+            }
+            int nc = 0;
+            for (int t = 0; t < len; t++) {
+                int k = list[t];
+                double l = w[k] / Lv[Lrp[k + 1] - 1];
+                w[k] = 0.0;
+                inw[k] = 0;
+                if (fabs(l) < taui[i]) continue;
+                cand[nc].col = k;
+                cand[nc].val = l;
+                nc++;
+                for (int e = head[k]; e >= 0; e = nxt[e]) {
+                    int m = Lrow[e];
+                    if (!inw[m]) { /* fill: insert m into the ascending tail of the list */
+                        int p = len++;
+                        while (p > t + 1 && list[p - 1] > m) { list[p] = list[p - 1]; p--; }
+                        list[p] = m;
+                        inw[m] = 1;
+                    }
+                    w[m] -= l * Lv[e];
+                }
+            }
+            if (nc > lfil) {
+                qsort(cand, (size_t)nc, sizeof(ict_ent), ict_by_size);
+                nc = lfil;
+                qsort(cand, (size_t)nc, sizeof(ict_ent), ict_by_col);
+            }
+            double d = ds[i];
+            for (int t = 0; t < nc; t++) d -= cand[t].val * cand[t].val;
+            if (!(d > 0.0)) { ok = 0; break; }
+            if (nz + (size_t)nc + 1 > cap) {
+                cap = 2 * cap + (size_t)nc + 1;
+                Lci = realloc(Lci, sizeof(int) * cap);
+                Lrow = realloc(Lrow, sizeof(int) * cap);
+                nxt = realloc(nxt, sizeof(int) * cap);
+                Lv = realloc(Lv, sizeof(double) * cap);
+            }
+            for (int t = 0; t < nc; t++) {
+                int k = cand[t].col;
+                Lci[nz] = k;
+                Lrow[nz] = i;
+                Lv[nz] = cand[t].val;
+                nxt[nz] = -1;
+                if (tail[k] < 0) head[k] = (int)nz;
+                else nxt[tail[k]] = (int)nz;
+                tail[k] = (int)nz;
+                nz++;
+            }
+            Lci[nz] = i;
+            Lrow[nz] = i;
+            Lv[nz] = sqrt(d);
+            nxt[nz] = -1;
+            nz++;
+            Lrp[i + 1] = (int)nz;
+        }
+        if (ok) break;
+        a = (a == 0.0) ? shift0 : 2.0 * a;
+        if (a > shift_max || shift0 <= 0.0) { rc = -1; break; }
+    }
+    if (rc == 0) {
+        for (int i = 0; i < n; i++)
+            for (int e = Lrp[i]; e < Lrp[i + 1]; e++) Lv[e] *= sq[i];
+        *Lrp_out = Lrp;
+        *Lci_out = Lci;
+        *Lv_out = Lv;
+        if (shift_used) *shift_used = a;
+    } else {
+        free(Lrp); free(Lci); free(Lv);
+    }
+    free(Lrow); free(nxt); free(dg); free(ds); free(r); free(sq); free(taui); free(w); free(inw); free(list); free(cand);
+    free(head); free(tail);
+    return rc;
 }
 
 /* Forward substitution L x = b (L rows, diagonal last). */
@@ -417,11 +591,21 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
     if (p < 1 || p > OR_MAXP || n < 1) return -1;
     double t0 = now_s();
     int nnzL = or_tril_nnz(n, rp, ci);
-    int *Lrp = malloc(sizeof(int) * (size_t)(n + 1));
-    int *Lci = malloc(sizeof(int) * (size_t)nnzL);
-    double *Lv = malloc(sizeof(double) * (size_t)nnzL);
-    int rc = or_ic0(n, rp, ci, v, o->shift0, o->shift_max, Lrp, Lci, Lv, &st->shift_used);
-    if (rc != 0) { free(Lrp); free(Lci); free(Lv); st->status = rc; return -2; }
+    int *Lrp, *Lci;
+    double *Lv;
+    int rc;
+    if (o->ict) {
+        rc = or_ict(n, rp, ci, v, o->lfil, o->tau_ic, o->shift0, o->shift_max, &Lrp, &Lci, &Lv, &st->shift_used);
+        if (rc != 0) { st->status = rc; return -2; }
+    } else {
+        Lrp = malloc(sizeof(int) * (size_t)(n + 1));
+        Lci = malloc(sizeof(int) * (size_t)nnzL);
+        Lv = malloc(sizeof(double) * (size_t)nnzL);
+        rc = or_ic0(n, rp, ci, v, o->shift0, o->shift_max, Lrp, Lci, Lv, &st->shift_used);
+        if (rc != 0) { free(Lrp); free(Lci); free(Lv); st->status = rc; return -2; }
+    }
+    st->nnz_L = Lrp[n];
+    st->fill = (double)Lrp[n] / (double)nnzL;
     st->t_factor = now_s() - t0;
 
     prob P = {n, rp, ci, v, Lrp, Lci, Lv, malloc(sizeof(double) * (size_t)n)};

@@ -487,3 +487,167 @@ def test_full_bfgs_pairs(oracle_lib):
     np.testing.assert_allclose(ev1, ev0, rtol=1e-10)
     assert st1["pcg_its"] != st0["pcg_its"]
     assert st1["status"] == 0
+
+
+# ----------------------------------------------------------------------------- IC(lfil, tau_IC) (Sec. 2)
+def _scaled(Ad):
+    """As = D^-1/2 A D^-1/2 and tau_i = ||As(i,:)||_2: the scaled matrix and row norms of the drop rule."""
+    r = 1.0 / np.sqrt(np.diag(Ad))
+    As = Ad * r[:, None] * r[None, :]
+    return As, np.linalg.norm(As, axis=1)
+
+
+def test_ict_limits_are_cholesky_and_jacobi(oracle_lib):
+    """tau_IC = 0 with unbounded lfil is the exact Cholesky factor (numpy); dropping everything (a huge tau
+    or lfil = 0) leaves L = diag(sqrt(a_ii))."""
+    for A in small_mats():
+        Ad = dense(A)
+        L = oracle_lib.ict(A, lfil=A.n, tau=0.0).dense()
+        Lc = np.linalg.cholesky(Ad)
+        assert np.abs(L - Lc).max() <= 1e-12 * np.abs(Lc).max()
+        for lf, tau in ((A.n, 1e300), (0, 0.0)):
+            F = oracle_lib.ict(A, lfil=lf, tau=tau)
+            assert len(F.val) == A.n
+            np.testing.assert_allclose(F.dense(), np.diag(np.sqrt(np.diag(Ad))), rtol=4e-16, atol=0)
+
+
+@pytest.mark.parametrize("tau", [1e-3, 1e-2, 1e-1])
+def test_ict_threshold_rule_characterisation(oracle_lib, tau):
+    """With lfil unbounded the factor is fixed by the threshold rule alone: with Ls = D^-1/2 L,
+    kept entries satisfy |Ls_ij| >= tau_i and (Ls Ls^T)_ij = As_ij (and the diagonal always matches);
+    every dropped position j < i has |As_ij - (Ls Ls^T)_ij| / Ls_jj < tau_i, which is the value the
+    entry would have had."""
+    for A in small_mats():
+        Ad = dense(A)
+        As, nrm = _scaled(Ad)
+        ti = tau * nrm
+        F = oracle_lib.ict(A, lfil=A.n, tau=tau)
+        assert F.shift == 0.0
+        L = F.dense()
+        Ls = L / np.sqrt(np.diag(Ad))[:, None]
+        kept = np.zeros_like(L, dtype=bool)
+        for i in range(A.n):
+            kept[i, F.col[F.rowptr[i]:F.rowptr[i + 1]]] = True
+        M = Ls @ Ls.T
+        low = np.tril(np.ones_like(kept), -1).astype(bool)
+        I, J = np.nonzero(kept & low)
+        assert np.all(np.abs(Ls[I, J]) >= ti[I] * (1 - 1e-12))
+        assert np.abs(M[I, J] - As[I, J]).max(initial=0) <= 1e-12
+        np.testing.assert_allclose(np.diag(M), np.diag(As), rtol=1e-13)
+        I, J = np.nonzero(~kept & low)
+        would = np.abs(As[I, J] - M[I, J]) / np.diag(Ls)[J]
+        assert np.all(would < ti[I] * (1 + 1e-9) + 1e-14)
+        if tau == 1e-3 and A.n > 200:
+            assert len(F.val) > (A.nnz + A.n) // 2  # fill beyond the pattern of tril(A)
+
+
+def _ict_dense(Ad, lfil, tau):
+    """The IC(lfil, tau_IC) rule on dense arrays, pure-Python loops (tiny inputs only)."""
+    n = len(Ad)
+    As, nrm = _scaled(Ad)
+    ti = tau * nrm
+    Ls = np.zeros((n, n))
+    kept = np.zeros((n, n), dtype=bool)
+    for i in range(n):
+        w = As[i, :i].copy()
+        live = w != 0
+        cand = []
+        for k in range(i):
+            if not live[k]:
+                continue
+            lik = w[k] / Ls[k, k]
+            if abs(lik) < ti[i]:
+                continue
+            cand.append((k, lik))
+            for m in range(k + 1, i):
+                if kept[m, k]:
+                    w[m] -= lik * Ls[m, k]
+                    live[m] = True
+        sel = sorted(sorted(cand, key=lambda c: (-abs(c[1]), c[0]))[:lfil])
+        d = As[i, i]
+        for k, lik in sel:
+            Ls[i, k] = lik
+            kept[i, k] = True
+            d -= lik * lik
+        assert d > 0
+        Ls[i, i] = np.sqrt(d)
+        kept[i, i] = True
+    return Ls * np.sqrt(np.diag(Ad))[:, None], kept
+
+
+def _random_spd(n, density, seed, ridge=0.5):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n)) * (rng.random((n, n)) < density)
+    Ad = M @ M.T + ridge * np.eye(n)
+    return Ad
+
+
+@pytest.mark.parametrize("lfil,tau", [(1, 0.0), (2, 0.0), (4, 0.05), (3, 0.2), (40, 0.05)])
+def test_ict_matches_dense_brute_force(oracle_lib, lfil, tau):
+    """The lfil rule (keep the lfil largest candidates, ties to the smaller column) and fill creation
+    against a dense pure-Python run of the same rule; no row of L holds more than lfil off-diagonal
+    entries."""
+    for Ad in (_random_spd(40, 0.1, 7), dense(W.laplacian_2d(6)), _random_spd(30, 0.3, 8, ridge=2.0)):
+        A = W._from_scipy(sp.csr_matrix(Ad))
+        F = oracle_lib.ict(A, lfil=lfil, tau=tau)
+        assert F.shift == 0.0
+        Lb, kb = _ict_dense(Ad, lfil, tau)
+        L = F.dense()
+        k = np.zeros_like(kb)
+        for i in range(A.n):
+            k[i, F.col[F.rowptr[i]:F.rowptr[i + 1]]] = True
+        assert np.array_equal(k, kb)
+        assert np.abs(L - Lb).max() <= 1e-12 * np.abs(Lb).max()
+        assert np.diff(F.rowptr).max() <= lfil + 1
+
+
+def test_ict_breakdown_restarts_on_shifted_matrix(oracle_lib):
+    """A non-positive pivot restarts the factorisation on A + a diag(A), a = shift0 2^m: the result is
+    bit-identical to the unshifted factor of that matrix, and the previous shift of the schedule breaks
+    down."""
+    found = 0
+    for seed in range(200):
+        Ad = _random_spd(8, 0.4, seed, ridge=0.05)
+        A = W._from_scipy(sp.csr_matrix(Ad))
+        try:
+            F = oracle_lib.ict(A, lfil=2, tau=0.0, shift0=1e-3, shift_max=1.0)
+        except RuntimeError:
+            continue
+        if F.shift == 0.0:
+            continue
+        m = np.log2(F.shift / 1e-3)
+        assert abs(m - round(m)) < 1e-12
+        def shifted(a):
+            B = W._from_scipy(sp.csr_matrix(Ad))
+            dia = B.col == np.repeat(np.arange(B.n), np.diff(B.rowptr))
+            B.val = B.val.copy()
+            B.val[dia] = B.val[dia] * (1.0 + a)
+            return B
+        G = oracle_lib.ict(shifted(F.shift), lfil=2, tau=0.0, shift0=0.0)
+        assert np.array_equal(G.rowptr, F.rowptr) and np.array_equal(G.col, F.col)
+        assert np.array_equal(G.val, F.val)
+        prev = F.shift / 2 if F.shift > 1e-3 else 0.0
+        with pytest.raises(RuntimeError):
+            oracle_lib.ict(shifted(prev), lfil=2, tau=0.0, shift0=0.0)
+        found += 1
+        if found == 3:
+            break
+    assert found == 3
+
+
+def test_solve_with_ict_preconditioner(oracle_lib):
+    """IC(lfil, tau_IC) changes the preconditioner, not the eigenpairs: closed-form Laplacian eigenvalues,
+    the IC(0) eigenvalues on a diffusion matrix, and the fill ratio sigma of Sec. 5 reported."""
+    A, p = W.config_small()
+    ev, Vr, st, _ = oracle_lib.solve(A, p, ict=1, lfil=30, tau_ic=1e-2)
+    np.testing.assert_allclose(ev, W.laplacian_2d_eigs(32)[:p], rtol=1e-10)
+    _check_pairs(A, ev, Vr)
+    assert st["fill"] == pytest.approx(st["nnz_L"] / ((A.nnz + A.n) // 2))
+    assert st["fill"] > 1.0
+    B = W.diffusion_3d(12, seed=1)
+    ev0, _, st0, _ = oracle_lib.solve(B, 4)
+    assert st0["fill"] == 1.0
+    for lf, tau in ((10, 0.1), (30, 1e-2), (50, 1e-4)):
+        ev1, V1, st1, _ = oracle_lib.solve(B, 4, ict=1, lfil=lf, tau_ic=tau)
+        np.testing.assert_allclose(ev1, ev0, rtol=1e-10)
+        _check_pairs(B, ev1, V1)
