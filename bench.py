@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--newton", type=int, default=1,
                     help="1: DACG-Newton (the method); 0: DACG alone to the same tolerance (the paper's DACG rows)")
+    ap.add_argument("--ict", type=str, default="",
+                    help="'LFIL,TAU': precondition with IC(lfil, tau_IC) instead of IC(0) (the paper's own initial "
+                         "preconditioner; Table 2 defaults are 30,1e-2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -136,9 +139,18 @@ def main():
     torch.cuda.set_device(0)
     S = bnx.Solver(A.rowptr, A.col, A.val)
     bnx.bnx_set_trsv_mode(S.h, args.trsv_mode)
-    S.factor()
+    fkw = {}
+    if args.ict:
+        lf, tau = args.ict.split(",")
+        fkw = dict(ict=1, lfil=int(lf), tau_ic=float(tau))
+    t0 = time.time()
+    S.factor(**fkw)
+    print(f"[bench] factor {'IC(%s)' % args.ict if args.ict else 'IC(0)'}: {time.time() - t0:.2f}s", flush=True)
     x0d = torch.as_tensor(x0).cuda()
-    nnzL = (A.nnz + A.n) // 2
+    finfo = bnx.bnx_factor_info(S.h)
+    nnzL = finfo["nnz_L"]
+    print(f"[bench] factor: nnz(L) {nnzL}, sigma {finfo['fill']:.3f}, levels {finfo['levels_L']} / "
+          f"{finfo['levels_Lt']}", flush=True)
     if args.kernels:
         kernel_probe(args, A, S, nnzL, bnx, torch)
         return
@@ -152,7 +164,7 @@ def main():
     results = {}
     for name, prec in (("mixed", bnx.MIXED), ("fp64", bnx.FP64)):
         for w in range(args.warmup):
-            S.factor()
+            S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
             print(f"[bench] warmup {name} {w}: {st['t_dacg'] + st['t_newton']:.3f}s status {st['status']}",
                   flush=True)
@@ -161,7 +173,7 @@ def main():
         t0 = time.perf_counter()
         stats = []
         for k in range(args.steps):
-            S.factor()
+            S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
             stats.append(st)
             print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
@@ -239,7 +251,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"diffusion3d_{N}^3_lognormal_seed1", "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
                    "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
-                   "method": "DACG-Newton" if args.newton else "DACG alone"},
+                   "method": "DACG-Newton" if args.newton else "DACG alone",
+                   "preconditioner": f"IC({args.ict})" if args.ict else "IC(0)",
+                   "fill_sigma": round(mixed["stats"]["fill"], 4)},
         "fp64": {"value": round(fp64["eps"], 4), "ms_per_step": round(fp64["ms"], 2), "max_relres": fp64["relres"],
                  "pcg_its": sum(fp64["stats"]["pcg_its"]), "outer_its": sum(fp64["stats"]["outer_its"]),
                  "dacg_its": sum(fp64["stats"]["dacg_its"])},

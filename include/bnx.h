@@ -79,11 +79,20 @@ typedef struct {
                            skipped unless s_k^T y_k > 0                                  (0) */
 } bnx_solve_opts;
 
-/* IC(0) breakdown policy (Sec. 2 initial preconditioner): on a non-positive pivot
- * the factor is recomputed for A + a*diag(A), a = shift0, 2*shift0, ... <= shift_max. */
+/* Initial preconditioner P0^ = (L L^T)^{-1} of Sec. 2.  Breakdown policy: on a
+ * non-positive pivot the factor is recomputed for A + a*diag(A),
+ * a = shift0, 2*shift0, ... <= shift_max. */
 typedef struct {
     double shift0;      /* (1e-3) */
     double shift_max;   /* (1.0); shift0 <= 0 disables the retry */
+    int ict;            /* 0: IC(0) on the pattern of tril(A), computed on the device (0);
+                           1: IC(lfil, tau_ic), the threshold factor the paper uses: at most
+                           lfil entries off the diagonal per row of L, entries below tau_ic
+                           (relative to the row norm of D^-1/2 A D^-1/2) dropped.  Computed on
+                           the host -- its pattern depends on the values row by row -- and
+                           installed with its own level sets and block schedules */
+    int lfil;           /* (30, Table 2); >= 0 */
+    double tau_ic;      /* (1e-2, Table 2); >= 0 */
 } bnx_factor_opts;
 
 /* Counters mirroring the columns of the paper's result tables (Tables 4-8). */
@@ -102,6 +111,8 @@ typedef struct {
     double shift_used;          /* IC(0) diagonal shift actually used */
     double t_factor, t_dacg, t_newton;  /* seconds */
     int dacg_restarts;          /* returns from a stalled Newton phase to DACG (see bnx_solve) */
+    long long nnz_L;            /* entries of the factor L, diagonal included */
+    double fill;                /* fill ratio sigma of Sec. 5: nnz(L) / nnz(tril(A)) */
 } bnx_stats;
 
 void bnx_default_solve_opts(bnx_solve_opts *o);
@@ -128,12 +139,22 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
 bnx_status bnx_set_values(bnx_ctx *ctx, const double *val);
 
 /*
- * IC(0) factor L, L L^T = A on the pattern of tril(A) (Sec. 2, P0^ = (L L^T)^{-1}),
- * computed on the device level by level, plus the level schedules of the
- * L and L^T solves.  opts may be NULL (defaults).
- * Errors: BNX_E_NOT_SPD when every shift up to shift_max breaks down.
+ * Incomplete Cholesky factor L of the initial preconditioner (Sec. 2,
+ * P0^ = (L L^T)^{-1}): IC(0), L L^T = A on the pattern of tril(A), computed on
+ * the device level by level; or IC(lfil, tau_ic) (opts->ict = 1).  Also the
+ * level sets and LDS block schedules of the L and L^T solves for the pattern of
+ * L (rebuilt when the pattern changes).  opts may be NULL (defaults: IC(0)).
+ * Errors: BNX_E_ARG (lfil < 0 or tau_ic < 0), BNX_E_NOT_SPD when every shift up
+ * to shift_max breaks down.
  */
 bnx_status bnx_factor(bnx_ctx *ctx, const bnx_factor_opts *opts);
+
+/* Size of the installed factor (Sec. 5 reports the fill ratio sigma of the
+ * initial preconditioner): nnz(L) with the diagonal, sigma = nnz(L)/nnz(tril A),
+ * the dependency levels of the L and L^T solves and the diagonal shift used.
+ * Any output pointer may be NULL.  Errors: BNX_E_ARG, BNX_E_STATE before bnx_factor. */
+bnx_status bnx_factor_info(const bnx_ctx *ctx, long long *nnz_L, double *fill, int *levels_L, int *levels_Lt,
+                           double *shift_used);
 
 /*
  * The p leftmost eigenpairs by DACG-Newton (Alg. 2).

@@ -34,7 +34,8 @@ class SolveOpts(C.Structure):
 
 
 class FactorOpts(C.Structure):
-    _fields_ = [("shift0", C.c_double), ("shift_max", C.c_double)]
+    _fields_ = [("shift0", C.c_double), ("shift_max", C.c_double), ("ict", C.c_int), ("lfil", C.c_int),
+                ("tau_ic", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -43,7 +44,7 @@ class Stats(C.Structure):
                 ("mvp_newton", C.c_longlong), ("bfgs_skipped", C.c_int), ("pcg_breakdowns", C.c_int),
                 ("status", C.c_int), ("levels_L", C.c_int), ("levels_Lt", C.c_int), ("shift_used", C.c_double),
                 ("t_factor", C.c_double), ("t_dacg", C.c_double), ("t_newton", C.c_double),
-                ("dacg_restarts", C.c_int)]
+                ("dacg_restarts", C.c_int), ("nnz_L", C.c_longlong), ("fill", C.c_double)]
 
     def as_dict(self, p):
         return {"dacg_its": list(self.dacg_its[:p]), "outer_its": list(self.outer_its[:p]),
@@ -52,13 +53,13 @@ class Stats(C.Structure):
                 "bfgs_skipped": self.bfgs_skipped, "pcg_breakdowns": self.pcg_breakdowns, "status": self.status,
                 "levels_L": self.levels_L, "levels_Lt": self.levels_Lt, "shift_used": self.shift_used,
                 "t_factor": self.t_factor, "t_dacg": self.t_dacg, "t_newton": self.t_newton,
-                "dacg_restarts": self.dacg_restarts}
+                "dacg_restarts": self.dacg_restarts, "nnz_L": self.nnz_L, "fill": self.fill}
 
 
 EXPORTS = ["bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_create_csr", "bnx_set_values", "bnx_factor",
            "bnx_solve", "bnx_backward", "bnx_set_adjoint_params", "bnx_last_error", "bnx_destroy", "bnx_spmv",
            "bnx_ic_apply", "bnx_prec_apply", "bnx_correction_solve", "bnx_dacg", "bnx_set_trsv_mode",
-           "bnx_set_profiling", "bnx_kernel_time", "bnx_probe_latency"]
+           "bnx_set_profiling", "bnx_kernel_time", "bnx_probe_latency", "bnx_factor_info"]
 
 _lib = None
 _vp = C.c_void_p
@@ -97,6 +98,8 @@ def load(path: str = LIBPATH):
     L.bnx_set_profiling.argtypes = [_vp, C.c_int]
     L.bnx_kernel_time.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
     L.bnx_probe_latency.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.bnx_factor_info.argtypes = [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int), C.POINTER(C.c_double)]
     for f in EXPORTS:
         if f not in ("bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_last_error", "bnx_destroy"):
             getattr(L, f).restype = C.c_int
@@ -201,6 +204,14 @@ def bnx_set_trsv_mode(h, mode):
     return _check(h, load().bnx_set_trsv_mode(h, mode))
 
 
+def bnx_factor_info(h) -> dict:
+    """nnz(L), fill ratio sigma, levels of the two solves and the shift of the installed factor."""
+    nz, fill, ll, lt, sh = C.c_longlong(), C.c_double(), C.c_int(), C.c_int(), C.c_double()
+    _check(h, load().bnx_factor_info(h, C.byref(nz), C.byref(fill), C.byref(ll), C.byref(lt), C.byref(sh)))
+    return {"nnz_L": nz.value, "fill": fill.value, "levels_L": ll.value, "levels_Lt": lt.value,
+            "shift_used": sh.value}
+
+
 def bnx_probe_latency(h, kind, hops):
     """Microseconds per dependent hand-over: kind 0 LDS between waves, 1 global flag between workgroups."""
     us = C.c_double()
@@ -255,8 +266,9 @@ class Solver:
         bnx_set_values(self.h, val)
         self.factored = False
 
-    def factor(self, shift0=1e-3, shift_max=1.0):
-        bnx_factor(self.h, FactorOpts(shift0, shift_max))
+    def factor(self, shift0=1e-3, shift_max=1.0, ict=0, lfil=30, tau_ic=1e-2):
+        """IC(0) (ict=0) or IC(lfil, tau_ic) (ict=1) initial preconditioner (Sec. 2)."""
+        bnx_factor(self.h, FactorOpts(shift0, shift_max, ict, lfil, tau_ic))
         self.factored = True
 
     def solve(self, p, precision=FP64, x0=None, **kw):

@@ -140,6 +140,18 @@ bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::ve
 void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
                     BlockSched &bs);
 
+// IC(lfil, tau_IC) factor of A + shift diag(A) (Sec. 2 initial preconditioner) in
+// CSR, rows with ascending columns and the diagonal last.  The dropping rule is
+// spelled out in ict.hip.  Returns false on a non-positive pivot.
+struct IctFactor {
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+};
+bool ict_factor(int n, const int *rp, const int *ci, const double *val, int lfil, double tau, double shift,
+                IctFactor &L);
+// Analysis input (the symmetric pattern L + L^T) whose tril is the pattern of L.
+void pattern_of_factor(int n, const IctFactor &L, Analysis &an);
+
 // ----------------------------------------------------------------- launchers
 int spmv_group(double mean_nnz);
 

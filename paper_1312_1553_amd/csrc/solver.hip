@@ -856,7 +856,9 @@ struct bnx_ctx {
   int n = 0, nnz = 0, device_ptrs = 0;
   hipStream_t st = nullptr;
   std::string err;
-  Analysis an;
+  Analysis an;                 // A, and the IC(0) pattern tril(A)
+  Analysis anT;                // pattern of the last IC(lfil, tau_IC) factor
+  const Analysis *ta = nullptr;  // pattern the device triangular structures hold (&an or &anT)
   int group = 8;
   // device arrays
   int *rp = nullptr, *ci = nullptr;
@@ -1020,7 +1022,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   F.ci = lower ? Lci : Ltci;
   F.v = lower ? Lv : Ltv;
   F.lev_rows = lower ? levL : levLt;
-  const Levels &lv = lower ? an.levL : an.levLt;
+  const Levels &lv = lower ? ta->levL : ta->levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
@@ -1062,7 +1064,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
   F.ci = lower ? Lci : Ltci;
   F.v = lower ? Lv32 : Ltv32;
   F.lev_rows = lower ? levL : levLt;
-  const Levels &lv = lower ? an.levL : an.levLt;
+  const Levels &lv = lower ? ta->levL : ta->levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
@@ -1675,8 +1677,10 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
   bool allc = true;
   for (int jj = 0; jj < p; jj++) allc = allc && So.converged[jj];
   So.status = allc ? BNX_OK : BNX_NOT_CONVERGED;
-  So.levels_L = C->an.levL.nlev;
-  So.levels_Lt = C->an.levLt.nlev;
+  So.levels_L = C->ta->levL.nlev;
+  So.levels_Lt = C->ta->levLt.nlev;
+  So.nnz_L = C->ta->nnzL;
+  So.fill = (double)C->ta->nnzL / (double)C->an.nnzL;
   So.shift_used = C->shift_used;
   So.t_factor = C->t_factor;
   if (st) *st = So;
@@ -1828,33 +1832,150 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
 }
 
 // ------------------------------------------------------------------ factor
-void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
-  const double t0 = now_s();
-  Analysis &an = C->an;
-  const int n = C->n;
-  const int nnzL = an.nnzL;
-  if (!C->Lrp) {
-    C->Lrp = C->alloc<int>(n + 1);
-    C->Lci = C->alloc<int>(nnzL);
-    C->mapL = C->alloc<int>(nnzL);
-    C->Ltrp = C->alloc<int>(n + 1);
-    C->Ltci = C->alloc<int>(nnzL);
-    C->mapLt = C->alloc<int>(nnzL);
-    C->levL = C->alloc<int>(n);
-    C->levLt = C->alloc<int>(n);
-    C->Lv = C->alloc<double>(nnzL);
-    C->Ltv = C->alloc<double>(nnzL);
-    C->Lv32 = C->alloc<float>(nnzL);
-    C->Ltv32 = C->alloc<float>(nnzL);
-    HIPCHK(hipMemcpyAsync(C->Lrp, an.Lrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->Lci, an.Lci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->mapL, an.mapL.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->Ltrp, an.Ltrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->Ltci, an.Ltci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->mapLt, an.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->levL, an.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
-    HIPCHK(hipMemcpyAsync(C->levLt, an.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+// Device copy of a triangular pattern (rows of L and of L^T, level sets) and the
+// LDS block schedules of its two solves, replacing whatever pattern was there.
+// Values are filled in by the factorisation.
+void build_tri(bnx_ctx *C, const Analysis &a) {
+  C->sync();
+  for (int dir = 0; dir < 2; dir++)
+    for (int pr = 0; pr < 2; pr++) {
+      auto &b = C->blk[dir][pr];
+      for (int *q : {b.bptr, b.brows, b.iptr, b.isrc, b.eptr, b.erank, b.orow, b.oslot, b.perm, b.slice_ptr,
+                     b.slice_nnz, b.ref, b.valmap, b.diagmap, b.cnt, b.ref4, b.valmap4})
+        C->release(q);
+      for (double *q : {b.diag64, b.val64, b.val4_64}) C->release(q);
+      for (float *q : {b.diag32, b.val32, b.val4_32}) C->release(q);
+      b = bnx_ctx::BlkDev{};
+    }
+  for (int *q : {C->Lrp, C->Lci, C->mapL, C->Ltrp, C->Ltci, C->mapLt, C->levL, C->levLt}) C->release(q);
+  for (double *q : {C->Lv, C->Ltv, C->blk_rhs, C->blk_exp}) C->release(q);
+  for (float *q : {C->Lv32, C->Ltv32}) C->release(q);
+  C->ta = nullptr;
+  C->factored = false;
+  C->solved = false;
+  const int n = a.n;
+  const int nnzL = a.nnzL;
+  C->Lrp = C->alloc<int>(n + 1);
+  C->Lci = C->alloc<int>(nnzL);
+  C->mapL = C->alloc<int>(nnzL);
+  C->Ltrp = C->alloc<int>(n + 1);
+  C->Ltci = C->alloc<int>(nnzL);
+  C->mapLt = C->alloc<int>(nnzL);
+  C->levL = C->alloc<int>(n);
+  C->levLt = C->alloc<int>(n);
+  C->Lv = C->alloc<double>(nnzL);
+  C->Ltv = C->alloc<double>(nnzL);
+  C->Lv32 = C->alloc<float>(nnzL);
+  C->Ltv32 = C->alloc<float>(nnzL);
+  HIPCHK(hipMemcpyAsync(C->Lrp, a.Lrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->Lci, a.Lci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->mapL, a.mapL.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->Ltrp, a.Ltrp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->Ltci, a.Ltci.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->mapLt, a.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->levL, a.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->levLt, a.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+  for (int pr = 0; pr < 2; pr++) {
+    std::vector<int> prow, pstart;
+    // Block size target: larger blocks cross fewer block boundaries, smaller ones
+    // keep more waves per level busy; measured best near 7k (FP64) and 12k (FP32)
+    // rows on the 7-point 100^3 grid.
+    int cap = pr == 0 ? kBlkTarget64 : kBlkTarget32;
+    if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
+      cap = atoi(e);
+    cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
+    if (!partition_rows(a, cap, prow, pstart)) continue;  // no block schedule
+    for (int dir = 0; dir < 2; dir++) {
+      BlockSched bs;
+      block_schedule(a, dir == 0, prow, pstart, bs);
+      if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
+      auto &b = C->blk[dir][pr];
+      b.n = bs.n;
+      b.npad = bs.npad;
+      b.nblocks = bs.nblocks;
+      b.ell = bs.ell;
+      b.nexp = bs.nexp;
+      auto up = [&](const std::vector<int> &v) {
+        int *d = C->alloc<int>(std::max<size_t>(v.size(), 1));
+        if (!v.empty())
+          HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
+        return d;
+      };
+      b.bptr = up(bs.bptr);
+      b.brows = up(bs.brows);
+      b.iptr = up(bs.iptr);
+      b.isrc = up(bs.isrc);
+      b.eptr = up(bs.eptr);
+      b.erank = up(bs.erank);
+      b.orow = up(bs.orow);
+      b.oslot = up(bs.oslot);
+      b.perm = up(bs.perm);
+      b.slice_ptr = up(bs.slice_ptr);
+      b.slice_nnz = up(bs.slice_nnz);
+      b.ref = up(bs.ref);
+      b.valmap = up(bs.valmap);
+      b.diagmap = up(bs.diagmap);
+      b.cnt = up(bs.cnt);
+      b.ref4 = up(bs.ref4);
+      b.valmap4 = up(bs.valmap4);
+      const size_t np = (size_t)bs.npad;
+      if (pr == 0) {
+        b.diag64 = C->alloc<double>(np);
+        b.val64 = C->alloc<double>(std::max(bs.ell, 1));
+        b.val4_64 = C->alloc<double>((size_t)kNR * np);
+      } else {
+        b.diag32 = C->alloc<float>(np);
+        b.val32 = C->alloc<float>(std::max(bs.ell, 1));
+        b.val4_32 = C->alloc<float>((size_t)kNR * np);
+      }
+      C->sync();  // host vectors go out of scope
+    }
   }
+  {
+    int np = n;
+    for (int dir = 0; dir < 2; dir++)
+      for (int pr = 0; pr < 2; pr++) np = std::max(np, C->blk[dir][pr].npad);
+    C->blk_rhs = C->alloc<double>(np);
+    int ne = 1;
+    for (int dir = 0; dir < 2; dir++)
+      for (int pr = 0; pr < 2; pr++) ne = std::max(ne, C->blk[dir][pr].nexp);
+    C->blk_exp = C->alloc<double>(ne);
+  }
+  C->sync();
+  C->ta = &a;
+}
+
+void finish_factor(bnx_ctx *C);
+
+void factor_impl(bnx_ctx *C, const bnx_factor_opts &o) {
+  const double t0 = now_s();
+  const double shift0 = o.shift0, shift_max = o.shift_max;
+  const int n = C->n;
+  if (o.ict) {
+    // IC(lfil, tau_IC) on the host (ict.hip), then the device structures of its pattern
+    std::vector<double> hv(C->nnz);
+    HIPCHK(hipMemcpyAsync(hv.data(), C->val, sizeof(double) * C->nnz, hipMemcpyDeviceToHost, C->st));
+    C->sync();
+    IctFactor F;
+    double a = 0.0;
+    while (!ict_factor(n, C->an.rp.data(), C->an.ci.data(), hv.data(), o.lfil, o.tau_ic, a, F)) {
+      a = (a == 0.0) ? shift0 : 2.0 * a;
+      if (shift0 <= 0.0 || a > shift_max) throw ApiError{BNX_E_NOT_SPD, "IC(lfil, tau) breakdown beyond shift_max"};
+    }
+    pattern_of_factor(n, F, C->anT);
+    analyse(C->anT);
+    if (C->anT.Lci != F.ci) throw ApiError{BNX_E_STATE, "factor pattern mismatch"};
+    build_tri(C, C->anT);
+    HIPCHK(hipMemcpyAsync(C->Lv, F.v.data(), sizeof(double) * F.v.size(), hipMemcpyHostToDevice, C->st));
+    C->shift_used = a;
+    finish_factor(C);
+    C->sync();  // F goes out of scope
+    C->t_factor = now_s() - t0;
+    return;
+  }
+  if (C->ta != &C->an) build_tri(C, C->an);
+  const Analysis &an = C->an;
+  const int nnzL = an.nnzL;
   double a = 0.0;
   for (;;) {
     hipLaunchKernelGGL(k_ic0_gather, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapL, C->val, C->Lv);
@@ -1871,6 +1992,13 @@ void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
     if (shift0 <= 0.0 || a > shift_max) throw ApiError{BNX_E_NOT_SPD, "IC(0) breakdown beyond shift_max"};
   }
   C->shift_used = a;
+  finish_factor(C);
+  C->t_factor = now_s() - t0;
+}
+
+// L^T values, the FP32 copies and the block-schedule value arrays from L (C->Lv).
+void finish_factor(bnx_ctx *C) {
+  const int nnzL = C->ta->nnzL;
   hipLaunchKernelGGL(k_gather_d, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapLt, C->Lv, C->Ltv);
   launch_cast<double, float>(C->st, nnzL, C->Lv, C->Lv32);
   launch_cast<double, float>(C->st, nnzL, C->Ltv, C->Ltv32);
@@ -1898,7 +2026,6 @@ void factor_impl(bnx_ctx *C, double shift0, double shift_max) {
     }
   }
   C->sync();
-  C->t_factor = now_s() - t0;
   C->factored = true;
   C->solved = false;
 }
@@ -2122,6 +2249,9 @@ void bnx_default_factor_opts(bnx_factor_opts *o) {
   if (!o) return;
   o->shift0 = 1e-3;
   o->shift_max = 1.0;
+  o->ict = 0;
+  o->lfil = 30;
+  o->tau_ic = 1e-2;
 }
 
 bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *col,
@@ -2193,78 +2323,13 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
         C->sync();  // host vectors go out of scope
       }
     }
-    for (int pr = 0; pr < 2; pr++) {
-      std::vector<int> prow, pstart;
-      // Block size target: larger blocks cross fewer block boundaries, smaller ones
-      // keep more waves per level busy; measured best near 7k (FP64) and 12k (FP32)
-      // rows on the 7-point 100^3 grid.
-      int cap = pr == 0 ? kBlkTarget64 : kBlkTarget32;
-      if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
-        cap = atoi(e);
-      cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
-      if (!partition_rows(C->an, cap, prow, pstart)) continue;  // no block schedule
-      for (int dir = 0; dir < 2; dir++) {
-        BlockSched bs;
-        block_schedule(C->an, dir == 0, prow, pstart, bs);
-        if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
-        auto &b = C->blk[dir][pr];
-        b.n = bs.n;
-        b.npad = bs.npad;
-        b.nblocks = bs.nblocks;
-        b.ell = bs.ell;
-        b.nexp = bs.nexp;
-        auto up = [&](const std::vector<int> &v) {
-          int *d = C->alloc<int>(std::max<size_t>(v.size(), 1));
-          if (!v.empty())
-            HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
-          return d;
-        };
-        b.bptr = up(bs.bptr);
-        b.brows = up(bs.brows);
-        b.iptr = up(bs.iptr);
-        b.isrc = up(bs.isrc);
-        b.eptr = up(bs.eptr);
-        b.erank = up(bs.erank);
-        b.orow = up(bs.orow);
-        b.oslot = up(bs.oslot);
-        b.perm = up(bs.perm);
-        b.slice_ptr = up(bs.slice_ptr);
-        b.slice_nnz = up(bs.slice_nnz);
-        b.ref = up(bs.ref);
-        b.valmap = up(bs.valmap);
-        b.diagmap = up(bs.diagmap);
-        b.cnt = up(bs.cnt);
-        b.ref4 = up(bs.ref4);
-        b.valmap4 = up(bs.valmap4);
-        const size_t np = (size_t)bs.npad;
-        if (pr == 0) {
-          b.diag64 = C->alloc<double>(np);
-          b.val64 = C->alloc<double>(std::max(bs.ell, 1));
-          b.val4_64 = C->alloc<double>((size_t)kNR * np);
-        } else {
-          b.diag32 = C->alloc<float>(np);
-          b.val32 = C->alloc<float>(std::max(bs.ell, 1));
-          b.val4_32 = C->alloc<float>((size_t)kNR * np);
-        }
-        C->sync();  // host vectors go out of scope
-      }
-    }
+    build_tri(C, C->an);
     if (const char *e = getenv("BNX_SF_WAVES")) C->sf_waves = atoi(e);  // tuning override of the solve window
     C->rp = C->alloc<int>(n + 1);
     C->ci = C->alloc<int>(nnz);
     C->val = C->alloc<double>(nnz);
     C->val32 = C->alloc<float>(nnz);
     C->ctl = C->alloc<DevCtl>(1);
-    {
-      int np = n;
-      for (int dir = 0; dir < 2; dir++)
-        for (int pr = 0; pr < 2; pr++) np = std::max(np, C->blk[dir][pr].npad);
-      C->blk_rhs = C->alloc<double>(np);
-      int ne = 1;
-      for (int dir = 0; dir < 2; dir++)
-        for (int pr = 0; pr < 2; pr++) ne = std::max(ne, C->blk[dir][pr].nexp);
-      C->blk_exp = C->alloc<double>(ne);
-    }
     C->part = C->alloc<double>((size_t)kAreas * kPartSlots * kNBMax);
     C->counter = C->alloc<int>(4);
     HIPCHK(hipMemsetAsync(C->counter, 0, 4 * sizeof(int), C->st));
@@ -2300,10 +2365,23 @@ bnx_status bnx_factor(bnx_ctx *C, const bnx_factor_opts *opts) {
   bnx_factor_opts o;
   bnx_default_factor_opts(&o);
   if (opts) o = *opts;
+  if (o.ict && (o.lfil < 0 || !(o.tau_ic >= 0.0))) return BNX_E_ARG;
   return guarded(C, [&]() -> bnx_status {
-    factor_impl(C, o.shift0, o.shift_max);
+    factor_impl(C, o);
     return BNX_OK;
   });
+}
+
+bnx_status bnx_factor_info(const bnx_ctx *C, long long *nnz_L, double *fill, int *levels_L, int *levels_Lt,
+                           double *shift_used) {
+  if (!C) return BNX_E_ARG;
+  if (!C->factored || !C->ta) return BNX_E_STATE;
+  if (nnz_L) *nnz_L = C->ta->nnzL;
+  if (fill) *fill = (double)C->ta->nnzL / (double)C->an.nnzL;
+  if (levels_L) *levels_L = C->ta->levL.nlev;
+  if (levels_Lt) *levels_Lt = C->ta->levLt.nlev;
+  if (shift_used) *shift_used = C->shift_used;
+  return BNX_OK;
 }
 
 bnx_status bnx_solve(bnx_ctx *C, const bnx_solve_opts *opts, double *evals, double *evecs, bnx_stats *stats) {

@@ -52,7 +52,8 @@ int main(void) {
          offsetof(bnx_solve_opts, x0), offsetof(bnx_solve_opts, keep_bfgs), offsetof(bnx_solve_opts, newton),
          offsetof(bnx_solve_opts, bfgs_full), sizeof(bnx_stats), offsetof(bnx_stats, mvp_dacg),
          offsetof(bnx_stats, t_newton));
-  printf("%zu\n", sizeof(bnx_factor_opts));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(bnx_factor_opts), offsetof(bnx_factor_opts, lfil),
+         offsetof(bnx_factor_opts, tau_ic), offsetof(bnx_stats, nnz_L), offsetof(bnx_stats, fill));
   return 0;
 }
 '''
@@ -65,7 +66,8 @@ int main(void) {
     got = [int(x) for x in out]
     S, T = bnx.SolveOpts, bnx.Stats
     want = [ctypes.sizeof(S), S.seed.offset, S.x0.offset, S.keep_bfgs.offset, S.newton.offset, S.bfgs_full.offset,
-            ctypes.sizeof(T), T.mvp_dacg.offset, T.t_newton.offset, ctypes.sizeof(bnx.FactorOpts)]
+            ctypes.sizeof(T), T.mvp_dacg.offset, T.t_newton.offset, ctypes.sizeof(bnx.FactorOpts),
+            bnx.FactorOpts.lfil.offset, bnx.FactorOpts.tau_ic.offset, T.nnz_L.offset, T.fill.offset]
     assert got == want
 
 
@@ -77,6 +79,8 @@ def test_defaults_match_paper_table2(lib):
     assert o.tol == g["tau"] and o.itmax == g["itmax"] and o.tol_dacg == g["tau_dacg"]
     assert o.tol_pcg == g["tau_pcg"] and o.itmax_pcg == g["itmax_pcg"]
     assert o.kmax == 5 and o.precision == 0
+    f = bnx.bnx_default_factor_opts()
+    assert f.lfil == g["lfil"] and f.tau_ic == g["tau_ic"] and f.ict == 0
 
 
 def test_create_rejects_null_arguments(lib):

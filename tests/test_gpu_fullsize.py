@@ -190,3 +190,25 @@ def test_c4_backward_vs_oracle_finite_differences(oracle_mod):
             say(f"  d/dh {got:+.10e} fd {f:+.10e} err/scale {err:.2e}")
             assert err <= 1e-6, (got, f)
     S.close()
+
+
+def test_fullsize_c1_ict_solves(oracle_mod):
+    """IC(30, 1e-2) (Table 2's lfil and tau_IC) on the full C1 matrix: the host factor installed with its
+    own block schedules, L z = b, L^T c = b and both against the oracle's factor."""
+    A = W.diffusion_3d(100, seed=1)
+    say("case fullsize C1 ict", A.n, A.nnz)
+    S = bnx.Solver(A.rowptr, A.col, A.val)
+    S.factor(ict=1, lfil=30, tau_ic=1e-2)
+    F = oracle_mod.ict(A, 30, 1e-2)
+    x = np.random.default_rng(6).standard_normal(A.n)
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    refs = [oracle_mod.lsolve(F, x), oracle_mod.ltsolve(F, x), oracle_mod.ltsolve(F, oracle_mod.lsolve(F, x))]
+    for which in range(3):
+        bnx.bnx_ic_apply(S.h, FP64, which, dev(x), y)
+        e64 = np.abs(host(y) - refs[which]).max() / np.abs(refs[which]).max()
+        bnx.bnx_ic_apply(S.h, MIXED, which, dev(x), y)
+        e32 = np.abs(host(y) - refs[which]).max() / np.abs(refs[which]).max()
+        say(f"  solve {which}: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 < 1e-11, (which, e64)
+        assert e32 < 1e-5, (which, e32)
+    S.close()

@@ -410,3 +410,109 @@ def test_full_bfgs_matches_oracle(oracle_mod, name, p, kw):
         if prec == FP64:
             assert abs(sum(st["pcg_its"]) - sum(st_o["pcg_its"])) <= 0.1 * sum(st_o["pcg_its"]) + 2
     S.close()
+
+
+# ----------------------------------------------------------------------------- IC(lfil, tau_IC) (Sec. 2)
+ICT_CASES = [("laplace2d_32", 30, 1e-2), ("diffusion_12", 30, 1e-2), ("diffusion_12", 50, 1e-4),
+             ("diffusion_12", 10, 0.1), ("elasticity_3", 30, 1e-2), ("rgg_3000", 30, 1e-2),
+             ("diffusion_40", 30, 1e-2), ("diffusion_40", 50, 1e-4)]
+
+
+@pytest.mark.parametrize("name,lfil,tau", ICT_CASES)
+def test_ict_factor_and_solves(oracle_mod, name, lfil, tau):
+    """The host IC(lfil, tau_IC) factor installed with its own schedules: L z = b, L^T c = b and both,
+    through every solve path, against the oracle's factor and substitutions."""
+    A = mats()[name]
+    say("case ict", name, lfil, tau)
+    S = solver_for(A)
+    S.factor(ict=1, lfil=lfil, tau_ic=tau)
+    F = oracle_mod.ict(A, lfil, tau)
+    info = bnx.bnx_factor_info(S.h)
+    assert info["nnz_L"] == len(F.val) and info["shift_used"] == F.shift
+    assert info["fill"] == pytest.approx(len(F.val) / ((A.nnz + A.n) // 2), rel=1e-15)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    refs = [oracle_mod.lsolve(F, b), oracle_mod.ltsolve(F, b), oracle_mod.ltsolve(F, oracle_mod.lsolve(F, b))]
+    for mode in (0, 1, 2):
+        bnx.bnx_set_trsv_mode(S.h, mode)
+        for which in range(3):
+            bnx.bnx_ic_apply(S.h, FP64, which, dev(b), x)
+            err = np.abs(host(x) - refs[which]).max() / np.abs(refs[which]).max()
+            assert err < 1e-12, (mode, which, err)
+            bnx.bnx_ic_apply(S.h, MIXED, which, dev(b), x)
+            err = np.abs(host(x) - refs[which]).max() / np.abs(refs[which]).max()
+            assert err < 1e-4, (mode, which, err)
+    S.close()
+
+
+@pytest.mark.parametrize("name,p", [("laplace2d_32", 4), ("diffusion_12", 6), ("elasticity_3", 4)])
+def test_ict_solve_matches_oracle(oracle_mod, name, p):
+    """DACG-Newton preconditioned with IC(30, 1e-2) against the oracle run with the same factor:
+    eigenvalues, residuals, nnz(L) and sigma, and the fp64 PCG iteration total within 10 %."""
+    A = mats()[name]
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0, ict=1, lfil=30, tau_ic=1e-2)
+    S = solver_for(A)
+    S.factor(ict=1, lfil=30, tau_ic=1e-2)
+    for prec in (FP64, MIXED):
+        say("case ict solve", name, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        ev = ev.numpy()
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, host(V), 1e-8)
+        assert st["status"] == 0
+        assert st["nnz_L"] == st_o["nnz_L"] and st["fill"] == pytest.approx(st_o["fill"], rel=1e-15)
+        if prec == FP64:
+            assert abs(sum(st["pcg_its"]) - sum(st_o["pcg_its"])) <= 0.1 * sum(st_o["pcg_its"]) + 2
+    S.close()
+
+
+def test_ict_then_ic0_restores_pattern(oracle_mod):
+    """Switching the factor back to IC(0) reinstalls the tril(A) pattern and its schedules."""
+    A = mats()["diffusion_40"]
+    S = solver_for(A)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    for kind in ("ict", "ic0", "ict"):
+        say("case factor switch", kind)
+        if kind == "ict":
+            S.factor(ict=1, lfil=30, tau_ic=1e-2)
+            F = oracle_mod.ict(A, 30, 1e-2)
+        else:
+            S.factor()
+            F = oracle_mod.ic0(A)
+        ref = oracle_mod.ltsolve(F, oracle_mod.lsolve(F, b))
+        bnx.bnx_ic_apply(S.h, FP64, 2, dev(b), x)
+        assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+    S.close()
+
+
+def test_ict_shift_on_breakdown(oracle_mod):
+    """A breakdown of IC(2, 0) restarts on A + a diag(A): same shift schedule and factor as the oracle."""
+    import scipy.sparse as sp
+    for seed in range(200):
+        rng = np.random.default_rng(seed)
+        M = rng.standard_normal((8, 8)) * (rng.random((8, 8)) < 0.4)
+        Ad = M @ M.T + 0.05 * np.eye(8)
+        A = W._from_scipy(sp.csr_matrix(Ad))
+        try:
+            F = oracle_mod.ict(A, 2, 0.0, 1e-3, 1.0)
+        except RuntimeError:
+            continue
+        if F.shift > 0:
+            break
+    assert F.shift > 0
+    say("case ict shift", seed, F.shift)
+    S = solver_for(A)
+    S.factor(1e-3, 1.0, ict=1, lfil=2, tau_ic=0.0)
+    b = np.arange(1.0, 9.0)
+    x = torch.empty(8, dtype=torch.float64, device="cuda")
+    bnx.bnx_ic_apply(S.h, FP64, 2, dev(b), x)
+    np.testing.assert_allclose(host(x), oracle_mod.ltsolve(F, oracle_mod.lsolve(F, b)), rtol=1e-13)
+    ev, V, st = S.solve(2, precision=FP64)
+    assert st["shift_used"] == F.shift
+    with pytest.raises(bnx.BnxError) as ei:
+        S.factor(0.0, 0.0, ict=1, lfil=2, tau_ic=0.0)
+    assert ei.value.code == -2
+    S.close()
