@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--newton", type=int, default=1,
                     help="1: DACG-Newton (the method); 0: DACG alone to the same tolerance (the paper's DACG rows)")
+    ap.add_argument("--bfgs-full", type=int, default=0,
+                    help="1: store the pairs of the full BFGS update eq. (2.1), y_k = r_{k+1} - r_k; 0: the "
+                         "simplified update eq. (2.2) (default)")
     ap.add_argument("--ict", type=str, default="",
                     help="'LFIL,TAU': precondition with IC(lfil, tau_IC) instead of IC(0) (the paper's own initial "
                          "preconditioner; Table 2 defaults are 30,1e-2)")
@@ -165,7 +168,7 @@ def main():
     for name, prec in (("mixed", bnx.MIXED), ("fp64", bnx.FP64)):
         for w in range(args.warmup):
             S.factor(**fkw)
-            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full)
             print(f"[bench] warmup {name} {w}: {st['t_dacg'] + st['t_newton']:.3f}s status {st['status']}",
                   flush=True)
         bnx.bnx_set_profiling(S.h, 1)
@@ -174,7 +177,7 @@ def main():
         stats = []
         for k in range(args.steps):
             S.factor(**fkw)
-            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full)
             stats.append(st)
             print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
                   flush=True)
@@ -253,6 +256,7 @@ def main():
                    "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
                    "method": "DACG-Newton" if args.newton else "DACG alone",
                    "preconditioner": f"IC({args.ict})" if args.ict else "IC(0)",
+                   "bfgs_update": "eq. (2.1) full" if args.bfgs_full else "eq. (2.2) simplified",
                    "fill_sigma": round(mixed["stats"]["fill"], 4)},
         "fp64": {"value": round(fp64["eps"], 4), "ms_per_step": round(fp64["ms"], 2), "max_relres": fp64["relres"],
                  "pcg_its": sum(fp64["stats"]["pcg_its"]), "outer_its": sum(fp64["stats"]["outer_its"]),

@@ -183,14 +183,20 @@ struct Bisect {
   bool ok = true;
 
   Bisect(const Analysis &a, int c, std::vector<int> &r, std::vector<int> &p) : an(a), cap(c), rows(r), pstart(p) {}
+  const std::vector<int> *vl = nullptr, *vu = nullptr;  // virtual rows per row and direction (split schedules)
 
   bool fits(int a, int b) {
     if (b - a > cap) return false;
     ++stamp;
     for (int t = a; t < b; t++) stamp_in[rows[t]] = stamp;
     int imp_l = 0, imp_u = 0;
+    long virt_l = 0, virt_u = 0;
     for (int t = a; t < b; t++) {
       const int i = rows[t];
+      if (vl) {
+        virt_l += (*vl)[i];
+        virt_u += (*vu)[i];
+      }
       for (int q = an.Lrp[i]; q < an.Lrp[i + 1] - 1; q++) {
         const int j = an.Lci[q];
         if (stamp_in[j] != stamp && stamp_l[j] != stamp) {
@@ -206,7 +212,7 @@ struct Bisect {
         }
       }
     }
-    return (b - a) + std::max(imp_l, imp_u) + 1 <= cap;  // + the zero slot
+    return (b - a) + std::max(imp_l + virt_l, imp_u + virt_u) + 1 <= cap;  // + the zero slot
   }
   int value(int c, int i) const { return c < (int)coord.size() ? (*coord[c])[i] : i; }
   // threshold of coordinate c splitting rows[a, b) nearest to half; false if it cannot split
@@ -278,14 +284,29 @@ struct Bisect {
 };
 }  // namespace
 
-bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart) {
+int virtual_rows(int deps) { return deps <= kNR ? 0 : (deps - kNR + kNR - 2) / (kNR - 1); }
+
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split) {
   const int n = an.n;
+  std::vector<int> vl, vu;
+  if (split) {
+    vl.resize(n);
+    vu.resize(n);
+    for (int i = 0; i < n; i++) {
+      vl[i] = virtual_rows(an.Lrp[i + 1] - an.Lrp[i] - 1);
+      vu[i] = virtual_rows(an.Ltrp[i + 1] - an.Ltrp[i] - 1);
+    }
+  }
   std::vector<int> co[3];
   const int ncls = dag_coords(an, co);
   rows.resize(n);
   for (int i = 0; i < n; i++) rows[i] = i;
   pstart.assign(1, 0);
   Bisect bi(an, cap, rows, pstart);
+  if (split) {
+    bi.vl = &vl;
+    bi.vu = &vu;
+  }
   for (int c = 0; c < ncls; c++) bi.coord.push_back(&co[c]);
   bi.coord.push_back(&an.levL.level);
   bi.stamp_in.assign(n, 0);
@@ -297,59 +318,178 @@ bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::ve
 }
 
 void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
-                    BlockSched &bs) {
+                    BlockSched &bs, bool split) {
   const int n = an.n;
   const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
   const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
   const std::vector<int> &glev = lower ? an.levL.level : an.levLt.level;
+  const std::vector<int> &bylev = lower ? an.levL.rows : an.levLt.rows;
   const int nb = (int)pstart.size() - 1;
+  auto deps = [&](int i, int &e0, int &e1) {
+    e0 = lower ? rp[i] : rp[i] + 1;
+    e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
+  };
+  // Items: the rows (ids 0..n-1) and, for a split schedule, virtual rows (ids n..): a
+  // row with m > kNR dependencies keeps its kNR-1 last-arriving ones plus the partial
+  // sum of the rest, which a chain of virtual rows computes (the first sums kNR
+  // dependencies, each further one the previous partial and kNR-1 more).  A virtual
+  // row has right-hand side 0 and diagonal 1, so its value is -sum L_ij x_j, and its
+  // consumer reads it with weight -1 (valmap -2).  Edges list (source item, factor
+  // position or -2); each row's dependencies are in the order their values appear
+  // (ascending level, ties by position), so a long row consumes its entries as they
+  // arrive and the last to arrive is read last.
+  std::vector<int> rptr(n + 1, 0), rsrc, rval;
+  std::vector<int> vptr(1, 0), vsrc, vval, vown, vsub;
+  std::vector<int> order;
+  rsrc.reserve(rp[n]);
+  rval.reserve(rp[n]);
+  for (int i = 0; i < n; i++) {
+    int e0, e1;
+    deps(i, e0, e1);
+    order.resize(e1 - e0);
+    for (int q = e0; q < e1; q++) order[q - e0] = q;
+    std::sort(order.begin(), order.end(), [&](int a, int c) {
+      return glev[ci[a]] != glev[ci[c]] ? glev[ci[a]] < glev[ci[c]] : a < c;
+    });
+    const int m = e1 - e0;
+    const int nv = split ? virtual_rows(m) : 0;
+    int own0 = 0;  // first of the row's own entries in `order`
+    if (nv > 0) {
+      const int c = m - (kNR - 1);  // entries summed by the chain
+      int at = 0, prev = -1;
+      for (int v = 0; v < nv; v++) {
+        const int id = n + (int)vown.size();
+        const int take = std::min(c - at, v == 0 ? kNR : kNR - 1);
+        if (prev >= 0) {
+          vsrc.push_back(prev);
+          vval.push_back(-2);
+        }
+        for (int t = 0; t < take; t++) {
+          vsrc.push_back(ci[order[at + t]]);
+          vval.push_back(order[at + t]);
+        }
+        at += take;
+        vptr.push_back((int)vsrc.size());
+        vown.push_back(i);
+        vsub.push_back(v);
+        prev = id;
+      }
+      rsrc.push_back(prev);
+      rval.push_back(-2);
+      own0 = c;
+    }
+    for (int t = own0; t < m; t++) {
+      rsrc.push_back(ci[order[t]]);
+      rval.push_back(order[t]);
+    }
+    rptr[i + 1] = (int)rsrc.size();
+  }
+  const int nvirt = (int)vown.size();
+  const int nitem = n + nvirt;
+  auto edges = [&](int it, const int *&src, const int *&val, int &cnt) {
+    if (it < n) {
+      src = rsrc.data() + rptr[it];
+      val = rval.data() + rptr[it];
+      cnt = rptr[it + 1] - rptr[it];
+    } else {
+      const int v = it - n;
+      src = vsrc.data() + vptr[v];
+      val = vval.data() + vptr[v];
+      cnt = vptr[v + 1] - vptr[v];
+    }
+  };
+  // levels of the item graph (the rows' levels when nothing is split), rows in level order
+  std::vector<int> lx(nitem, 0), vfirst(n, -1);
+  for (int v = nvirt - 1; v >= 0; v--) vfirst[vown[v]] = v;
+  for (int i : bylev) {
+    if (vfirst[i] >= 0)
+      for (int v = vfirst[i]; v < nvirt && vown[v] == i; v++) {
+        const int *src, *val;
+        int cnt;
+        edges(n + v, src, val, cnt);
+        int l = 0;
+        for (int e = 0; e < cnt; e++) l = std::max(l, lx[src[e]] + 1);
+        lx[n + v] = l;
+      }
+    const int *src, *val;
+    int cnt;
+    edges(i, src, val, cnt);
+    int l = 0;
+    for (int e = 0; e < cnt; e++) l = std::max(l, lx[src[e]] + 1);
+    lx[i] = l;
+  }
+  auto owner = [&](int it) { return it < n ? it : vown[it - n]; };
   bs.n = n;
   bs.nblocks = nb;
   bs.bptr.assign(nb + 1, 0);
   bs.brows.assign(nb, 0);
+  bs.nreal.assign(nb, 0);
   auto src_of = [&](int b) { return lower ? b : nb - 1 - b; };
+  std::vector<int> nvb(nb, 0);
+  {
+    std::vector<int> pb(n, 0);
+    for (int b = 0; b < nb; b++)
+      for (int t = pstart[b]; t < pstart[b + 1]; t++) pb[rows[t]] = b;
+    for (int v = 0; v < nvirt; v++) nvb[pb[vown[v]]]++;
+  }
   for (int b = 0; b < nb; b++) {
-    bs.brows[b] = pstart[src_of(b) + 1] - pstart[src_of(b)];
+    const int s = src_of(b);
+    bs.nreal[b] = pstart[s + 1] - pstart[s];
+    bs.brows[b] = bs.nreal[b] + nvb[s];
     bs.bptr[b + 1] = bs.bptr[b] + (bs.brows[b] + 63) / 64 * 64;
   }
   const int npad = bs.bptr[nb];
   bs.npad = npad;
   bs.perm.assign(npad, -1);
   bs.diagmap.assign(npad, 0);
-  std::vector<int> rank(n, 0), blk(n, 0);
+  std::vector<int> item(npad, -1);  // item of rank k
+  std::vector<int> rank(nitem, 0), blk(nitem, 0);
   bs.max_local_levels = 0;
-  for (int b = 0; b < nb; b++) {
-    const int s = src_of(b);
-    std::vector<int> order(rows.begin() + pstart[s], rows.begin() + pstart[s + 1]);
-    // by level, ties in solve order
-    std::sort(order.begin(), order.end(), [&](int a, int c) {
-      return glev[a] != glev[c] ? glev[a] < glev[c] : (lower ? a < c : a > c);
-    });
-    for (int t = 0; t < (int)order.size(); t++) {
-      const int i = order[t], k = bs.bptr[b] + t;
-      bs.perm[k] = i;
-      rank[i] = k;
-      blk[i] = b;
-      bs.diagmap[k] = lower ? rp[i + 1] - 1 : rp[i];
+  {
+    std::vector<std::vector<int>> vof(nb);
+    std::vector<int> pb(n, 0);
+    for (int b = 0; b < nb; b++)
+      for (int t = pstart[b]; t < pstart[b + 1]; t++) pb[rows[t]] = b;
+    for (int v = 0; v < nvirt; v++) vof[pb[vown[v]]].push_back(n + v);
+    for (int b = 0; b < nb; b++) {
+      const int s = src_of(b);
+      std::vector<int> ord(rows.begin() + pstart[s], rows.begin() + pstart[s + 1]);
+      ord.insert(ord.end(), vof[s].begin(), vof[s].end());
+      // by level, ties in solve order of the owning rows, partials before their row
+      std::sort(ord.begin(), ord.end(), [&](int a, int c) {
+        if (lx[a] != lx[c]) return lx[a] < lx[c];
+        const int oa = owner(a), oc = owner(c);
+        if (oa != oc) return lower ? oa < oc : oa > oc;
+        const int sa = a < n ? INT32_MAX : vsub[a - n], sc = c < n ? INT32_MAX : vsub[c - n];
+        return sa < sc;
+      });
+      for (int t = 0; t < (int)ord.size(); t++) {
+        const int it = ord[t], k = bs.bptr[b] + t;
+        item[k] = it;
+        rank[it] = k;
+        blk[it] = b;
+        if (it < n) {
+          bs.perm[k] = it;
+          bs.diagmap[k] = lower ? rp[it + 1] - 1 : rp[it];
+        } else {
+          bs.diagmap[k] = -1;  // diagonal 1
+        }
+      }
+      if (!ord.empty()) bs.max_local_levels = std::max(bs.max_local_levels, lx[ord.back()] - lx[ord.front()] + 1);
     }
-    if (!order.empty())
-      bs.max_local_levels = std::max(bs.max_local_levels, glev[order.back()] - glev[order.front()] + 1);
   }
-  auto deps = [&](int i, int &e0, int &e1) {
-    e0 = lower ? rp[i] : rp[i] + 1;
-    e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
-  };
   // ELL slices of 64 ranks for the dependencies beyond kNR
   bs.nslices = npad / 64;
   bs.slice_ptr.assign(bs.nslices + 1, 0);
   bs.slice_nnz.assign(bs.nslices, 0);
   bs.cnt.assign(npad, 0);
   for (int k = 0; k < npad; k++) {
-    if (bs.perm[k] < 0) continue;
-    int e0, e1;
-    deps(bs.perm[k], e0, e1);
-    bs.cnt[k] = e1 - e0;
-    bs.slice_nnz[k / 64] = std::max(bs.slice_nnz[k / 64], e1 - e0 - kNR);
+    if (item[k] < 0) continue;
+    const int *src, *val;
+    int cnt;
+    edges(item[k], src, val, cnt);
+    bs.cnt[k] = cnt;
+    bs.slice_nnz[k / 64] = std::max(bs.slice_nnz[k / 64], cnt - kNR);
   }
   for (int sl = 0; sl < bs.nslices; sl++) bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * bs.slice_nnz[sl];
   // bit 30 of cnt flags the ranks of slices that hold rows longer than kNR
@@ -365,27 +505,19 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
   bs.irow.clear();
   bs.max_lds = 0;
   std::vector<int> imp_blk(n, -1), imp_slot(n, 0);
-  std::vector<int> order;
   for (int b = 0; b < nb; b++) {
     int nimp = 0;
     for (int k = bs.bptr[b]; k < bs.bptr[b] + bs.brows[b]; k++) {
-      int e0, e1;
-      deps(bs.perm[k], e0, e1);
+      const int *src, *val;
+      int cnt;
+      edges(item[k], src, val, cnt);
       const int sl = k / 64, lane = k % 64;
-      // dependencies by level: the ones that finish first come first, so a row consumes its
-      // entries as they arrive and the last to arrive is read last
-      order.resize(e1 - e0);
-      for (int q = e0; q < e1; q++) order[q - e0] = q;
-      std::sort(order.begin(), order.end(), [&](int a, int c) {
-        return glev[ci[a]] != glev[ci[c]] ? glev[ci[a]] < glev[ci[c]] : a < c;
-      });
-      for (int e = 0; e < e1 - e0; e++) {
-        const int q = order[e];
-        const int j = ci[q];
+      for (int e = 0; e < cnt; e++) {
+        const int j = src[e];
         int slot;
         if (blk[j] == b) {
           slot = rank[j] - bs.bptr[b];
-        } else {
+        } else {  // only rows are imported: a virtual row lives in its owner's block
           if (imp_blk[j] != b) {
             imp_blk[j] = b;
             imp_slot[j] = nimp++;
@@ -395,11 +527,11 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
         }
         if (e < kNR) {
           bs.ref4[(size_t)e * npad + k] = -slot - 1;
-          bs.valmap4[(size_t)e * npad + k] = q;
+          bs.valmap4[(size_t)e * npad + k] = val[e];
         } else {
           const int at = bs.slice_ptr[sl] + 64 * (e - kNR) + lane;
           bs.ref[at] = -slot - 1;
-          bs.valmap[at] = q;
+          bs.valmap[at] = val[e];
         }
       }
     }
@@ -419,7 +551,7 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
   bs.erank.clear();
   for (int b = 0; b < nb; b++) {
     for (int k = bs.bptr[b]; k < bs.bptr[b] + bs.brows[b]; k++)
-      if (exp_id[bs.perm[k]] == 0) {
+      if (bs.perm[k] >= 0 && exp_id[bs.perm[k]] == 0) {
         exp_id[bs.perm[k]] = (int)bs.erank.size() + 1;  // 1-based while numbering
         bs.erank.push_back(k - bs.bptr[b]);
       }
@@ -428,14 +560,19 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
   bs.nexp = (int)bs.erank.size();
   bs.isrc.resize(bs.nimp);
   for (int e = 0; e < bs.nimp; e++) bs.isrc[e] = exp_id[bs.irow[e]] - 1;
-  // output order: each block's rows by increasing row index
+  // output order: each block's rows by increasing row index, then its virtual rows (row -1)
   bs.orow.assign(npad, 0);
   bs.oslot.assign(npad, 0);
   for (int b = 0; b < nb; b++) {
-    std::vector<std::pair<int, int>> o;
-    o.reserve(bs.brows[b]);
-    for (int t = 0; t < bs.brows[b]; t++) o.push_back({bs.perm[bs.bptr[b] + t], t});
+    std::vector<std::pair<int, int>> o, v;
+    o.reserve(bs.nreal[b]);
+    for (int t = 0; t < bs.brows[b]; t++) {
+      const int r = bs.perm[bs.bptr[b] + t];
+      if (r >= 0) o.push_back({r, t});
+      else v.push_back({-1, t});
+    }
     std::sort(o.begin(), o.end());
+    o.insert(o.end(), v.begin(), v.end());
     for (int t = 0; t < bs.brows[b]; t++) {
       bs.orow[bs.bptr[b] + t] = o[t].first;
       bs.oslot[bs.bptr[b] + t] = o[t].second;

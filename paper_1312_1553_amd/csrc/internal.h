@@ -96,19 +96,21 @@ struct BlockSched {
   int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;
   int max_local_levels = 0, max_lds = 0;
   std::vector<int> bptr;       // nblocks+1: first (padded) rank of each block
-  std::vector<int> brows;      // nblocks: rows of each block
+  std::vector<int> brows;      // nblocks: LDS rows of each block (its rows, then their virtual rows)
+  std::vector<int> nreal;      // nblocks: rows of each block that are rows of the matrix
   std::vector<int> iptr;       // nblocks+1: imports of each block
   std::vector<int> irow;       // imported rows (original ids), in order of first use
   std::vector<int> isrc;       // export id of each import
   std::vector<int> eptr;       // nblocks+1: exports of each block
   std::vector<int> erank;      // local rank of each export
-  std::vector<int> orow, oslot;  // npad: rows of each block by increasing row index, and their local ranks
+  std::vector<int> orow, oslot;  // npad: rows of each block by increasing row index (then -1 for virtual
+                                 // rows), and their local ranks
   int nexp = 0;
-  std::vector<int> perm;       // npad: original row of rank k (-1: padding)
-  std::vector<int> diagmap;    // npad: factor value index of the diagonal of row perm[k]
+  std::vector<int> perm;       // npad: original row of rank k (-1: padding or a virtual row)
+  std::vector<int> diagmap;    // npad: factor value index of the diagonal of row perm[k] (-1: diagonal 1)
   std::vector<int> cnt;        // npad: number of dependencies of rank k (| kLongSlice)
   std::vector<int> ref4;       // kNR * npad
-  std::vector<int> valmap4;    // kNR * npad, -1 where unused
+  std::vector<int> valmap4;    // kNR * npad, -1 where unused, -2 for weight -1 (a partial sum)
   std::vector<int> slice_ptr;  // nslices+1
   std::vector<int> slice_nnz;  // nslices: entries beyond kNR
   std::vector<int> ref;        // ell entries
@@ -133,12 +135,17 @@ void analyse(Analysis &an);
 // direction).  Blocks are rows[pstart[b] .. pstart[b+1]-1], listed in a
 // topological order of the forward graph.  Returns false when a single row
 // does not fit.
-bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart);
+// split: rows with more than kNR dependencies in either direction are solved
+// through chains of virtual partial-sum rows (block_schedule), which take LDS
+// slots of their own.
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split);
+// Virtual partial-sum rows a row with `deps` dependencies takes in a split schedule.
+int virtual_rows(int deps);
 // Block schedule of the forward (lower = true: rows of L, diag last) or backward
 // (rows of L^T, diag first) solve over a partition from partition_rows (the
 // backward solve takes its blocks in reverse order).
 void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
-                    BlockSched &bs);
+                    BlockSched &bs, bool split);
 
 // IC(lfil, tau_IC) factor of A + shift diag(A) (Sec. 2 initial preconditioner) in
 // CSR, rows with ascending columns and the diagonal last.  The dropping rule is

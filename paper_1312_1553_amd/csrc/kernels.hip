@@ -704,7 +704,10 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   }
   // every row of the block is in LDS: write the solution once, in row order
   __syncthreads();
-  for (int t = threadIdx.x; t < nrow; t += 1024) x[F.orow[k0 + t]] = from_bits<T>(xs[F.oslot[k0 + t]]);
+  for (int t = threadIdx.x; t < nrow; t += 1024) {
+    const int r = F.orow[k0 + t];  // virtual rows (-1) come last and are not written
+    if (r >= 0) x[r] = from_bits<T>(xs[F.oslot[k0 + t]]);
+  }
 }
 
 // Latency probes: a chain of `hops` dependent hand-overs, timed as one launch.

@@ -758,14 +758,14 @@ template <typename T>
 __global__ void k_gather_blk(int m, const int *map, const double *src, T *dst) {
   GRIDLOOP(q, m) {
     const int j = map[q];
-    dst[q] = j >= 0 ? (T)src[j] : T(0);
+    dst[q] = j >= 0 ? (T)src[j] : (j == -2 ? T(-1) : T(0));  // -2: a virtual row's partial sum
   }
 }
 
 // reciprocal diagonal of a block schedule: dst[k] = 1 / src[map[k]] (rounded once, in double)
 template <typename T>
 __global__ void k_gather_rdiag(int m, const int *map, const double *src, T *dst) {
-  GRIDLOOP(q, m) dst[q] = (T)(1.0 / src[map[q]]);
+  GRIDLOOP(q, m) dst[q] = map[q] >= 0 ? (T)(1.0 / src[map[q]]) : T(1);  // -1: a virtual row
 }
 
 // ============================================================== output helpers
@@ -1875,6 +1875,10 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   HIPCHK(hipMemcpyAsync(C->mapLt, a.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levL, a.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levLt, a.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
+  // Long rows (more than kNR dependencies) through chains of virtual partial-sum rows, so
+  // every row of the block solve takes its branch-free four-slot path
+  bool split = true;
+  if (const char *e = getenv("BNX_SPLIT_LONG")) split = atoi(e) != 0;  // tuning override
   for (int pr = 0; pr < 2; pr++) {
     std::vector<int> prow, pstart;
     // Block size target: larger blocks cross fewer block boundaries, smaller ones
@@ -1884,10 +1888,10 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
       cap = atoi(e);
     cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
-    if (!partition_rows(a, cap, prow, pstart)) continue;  // no block schedule
+    if (!partition_rows(a, cap, prow, pstart, split)) continue;  // no block schedule
     for (int dir = 0; dir < 2; dir++) {
       BlockSched bs;
-      block_schedule(a, dir == 0, prow, pstart, bs);
+      block_schedule(a, dir == 0, prow, pstart, bs, split);
       if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
       auto &b = C->blk[dir][pr];
       b.n = bs.n;
@@ -1949,6 +1953,8 @@ void finish_factor(bnx_ctx *C);
 
 void factor_impl(bnx_ctx *C, const bnx_factor_opts &o) {
   const double t0 = now_s();
+  C->factored = false;  // a failed factorisation leaves no factor behind
+  C->solved = false;
   const double shift0 = o.shift0, shift_max = o.shift_max;
   const int n = C->n;
   if (o.ict) {
@@ -1962,10 +1968,14 @@ void factor_impl(bnx_ctx *C, const bnx_factor_opts &o) {
       a = (a == 0.0) ? shift0 : 2.0 * a;
       if (shift0 <= 0.0 || a > shift_max) throw ApiError{BNX_E_NOT_SPD, "IC(lfil, tau) breakdown beyond shift_max"};
     }
-    pattern_of_factor(n, F, C->anT);
-    analyse(C->anT);
-    if (C->anT.Lci != F.ci) throw ApiError{BNX_E_STATE, "factor pattern mismatch"};
-    build_tri(C, C->anT);
+    // the installed structures serve again when the pattern is the one they were built for
+    // (a refactor of the same values, or of values that drop the same entries)
+    if (C->ta != &C->anT || C->anT.Lrp != F.rp || C->anT.Lci != F.ci) {
+      pattern_of_factor(n, F, C->anT);
+      analyse(C->anT);
+      if (C->anT.Lci != F.ci) throw ApiError{BNX_E_STATE, "factor pattern mismatch"};
+      build_tri(C, C->anT);
+    }
     HIPCHK(hipMemcpyAsync(C->Lv, F.v.data(), sizeof(double) * F.v.size(), hipMemcpyHostToDevice, C->st));
     C->shift_used = a;
     finish_factor(C);
