@@ -516,3 +516,25 @@ def test_ict_shift_on_breakdown(oracle_mod):
         S.factor(0.0, 0.0, ict=1, lfil=2, tau_ic=0.0)
     assert ei.value.code == -2
     S.close()
+
+
+@pytest.mark.parametrize("name,fkw", [("elasticity_3", {}), ("rgg_3000", {}),
+                                      ("diffusion_12", dict(ict=1, lfil=30, tau_ic=1e-2))])
+def test_unsplit_long_rows(oracle_mod, name, fkw, monkeypatch):
+    """Schedules built without virtual rows (BNX_SPLIT_LONG=0) take the chunked long-row path of the
+    block solve; same parity bar as the default schedules."""
+    monkeypatch.setenv("BNX_SPLIT_LONG", "0")
+    A = mats()[name]
+    say("case unsplit", name, fkw)
+    S = solver_for(A)
+    S.factor(**fkw)
+    F = oracle_mod.ict(A, 30, 1e-2) if fkw else oracle_mod.ic0(A)
+    b = np.random.default_rng(4).standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    refs = [oracle_mod.lsolve(F, b), oracle_mod.ltsolve(F, b)]
+    for which in range(2):
+        bnx.bnx_ic_apply(S.h, FP64, which, dev(b), x)
+        assert np.abs(host(x) - refs[which]).max() <= 1e-12 * np.abs(refs[which]).max()
+        bnx.bnx_ic_apply(S.h, MIXED, which, dev(b), x)
+        assert np.abs(host(x) - refs[which]).max() <= 1e-4 * np.abs(refs[which]).max()
+    S.close()
