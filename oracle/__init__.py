@@ -32,7 +32,8 @@ class Opts(C.Structure):
                 ("kmax", C.c_int), ("exit_rule", C.c_int), ("tol", C.c_double), ("tol_dacg", C.c_double),
                 ("tol_pcg", C.c_double), ("exit_xi", C.c_double), ("shift0", C.c_double),
                 ("shift_max", C.c_double), ("newton", C.c_int), ("bfgs_full", C.c_int), ("ict", C.c_int),
-                ("lfil", C.c_int), ("tau_ic", C.c_double)]
+                ("lfil", C.c_int), ("tau_ic", C.c_double), ("jd", C.c_int), ("jd_mmin", C.c_int),
+                ("jd_mmax", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -75,6 +76,8 @@ def lib():
         L.or_ict.argtypes = [C.c_int, _pi, _pi, _pd, C.c_int, C.c_double, C.c_double, C.c_double, _ppi, _ppi,
                              _ppd, _pd]
         L.or_ict.restype = C.c_int
+        L.or_symeig.argtypes = [C.c_int, _pd, _pd, _pd]
+        L.or_symeig.restype = None
         L.or_free.argtypes = [C.c_void_p]
         L.or_free.restype = None
         L.or_lsolve.argtypes = [C.c_int, _pi, _pi, _pd, _pd, _pd]
@@ -114,10 +117,11 @@ def default_opts(p: int, **kw) -> Opts:
     tau_PCG 1e-2, IMAX_PCG 20) with k_max = 5 and the floor exit rule (xi = 0.1).
     newton=0 runs DACG alone to tau (the DACG rows of Tables 4, 5, 7 and 8); bfgs_full=1 stores the
     pairs of eq. (2.1) with y_k = r_{k+1} - r_k instead of the simplified y_k ~ -r_k of eq. (2.2); ict=1
-    preconditions with IC(lfil, tau_ic) (Sec. 2; lfil 30, tau_IC 1e-2 as in Table 2) instead of IC(0)."""
+    preconditions with IC(lfil, tau_ic) (Sec. 2; lfil 30, tau_IC 1e-2 as in Table 2) instead of IC(0); jd=1 runs
+    the Jacobi-Davidson outer iteration of Sec. 6 (m_min 5, m_max 10) with the same PCG as correction solver."""
     d = dict(p=p, itmax=100, itmax_dacg=5000, itmax_pcg=20, kmax=5, exit_rule=1, tol=1e-8, tol_dacg=1e-2,
              tol_pcg=1e-2, exit_xi=0.1, shift0=1e-3, shift_max=1.0, newton=1, bfgs_full=0, ict=0, lfil=30,
-             tau_ic=1e-2)
+             tau_ic=1e-2, jd=0, jd_mmin=5, jd_mmax=10)
     d.update(kw)
     return Opts(**d)
 
@@ -173,6 +177,15 @@ def ict(A, lfil=30, tau=1e-2, shift0=1e-3, shift_max=1.0) -> Factor:
     for q in (pLrp, pLci, pLv):
         lib().or_free(C.cast(q, C.c_void_p))
     return Factor(Lrp, Lci, Lv, sh.value)
+
+
+def symeig(H):
+    """Cyclic Jacobi eigen-decomposition of a small symmetric matrix: (ascending values, vectors as columns)."""
+    m = H.shape[0]
+    Hw = np.ascontiguousarray(H, dtype=np.float64).copy()
+    ev = np.empty(m); Y = np.empty(m * m)
+    lib().or_symeig(m, Hw.ctypes.data_as(_pd), ev.ctypes.data_as(_pd), Y.ctypes.data_as(_pd))
+    return ev, Y.reshape(m, m).T.copy()
 
 
 def lsolve(F: Factor, b):

@@ -58,6 +58,9 @@ typedef struct {
     int ict;       /* 0: IC(0) on the pattern of tril(A); 1: IC(lfil, tau_ic) of Sec. 2 (or_ict) */
     int lfil;
     double tau_ic;
+    int jd;        /* 1: Jacobi-Davidson outer iteration (Sec. 6) in place of DACG + Newton, with the same PCG
+                      (and the BFGS pairs when kmax > 0) as the correction solver */
+    int jd_mmin, jd_mmax; /* restart and maximum dimensions of the search space (5 and 10 in Sec. 6) */
 } or_opts;
 
 typedef struct {
@@ -577,11 +580,168 @@ static void pairs_push(pairs_t *W, const double *s, const double *r, double alph
 }
 
 /*
+ * Eigen-decomposition of a symmetric m x m matrix H (row-major, overwritten) by the
+ * cyclic Jacobi method: rotations annihilate each off-diagonal entry in turn until
+ * the off-diagonal mass is below 1e-30 of the total.  ev[0..m-1] ascending, Y
+ * column-major (column c = eigenvector of ev[c]).  Used for the Rayleigh-Ritz step.
+ */
+void or_symeig(int m, double *H, double *ev, double *Y) {
+    for (int i = 0; i < m; i++)
+        for (int c = 0; c < m; c++) Y[c * m + i] = (i == c);
+    for (int sweep = 0; sweep < 100; sweep++) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; i++)
+            for (int c = 0; c < m; c++) {
+                tot += H[i * m + c] * H[i * m + c];
+                if (i != c) off += H[i * m + c] * H[i * m + c];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int a = 0; a < m - 1; a++)
+            for (int b = a + 1; b < m; b++) {
+                double hab = H[a * m + b];
+                if (hab == 0.0) continue;
+                /* rotation angle that zeroes H[a][b]: tan(2 phi) = 2 h_ab / (h_bb - h_aa) */
+                double zeta = (H[b * m + b] - H[a * m + a]) / (2.0 * hab);
+                double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+                for (int k = 0; k < m; k++) { /* H <- H G (columns a, b) */
+                    double x = H[k * m + a], y = H[k * m + b];
+                    H[k * m + a] = cs * x - sn * y;
+                    H[k * m + b] = sn * x + cs * y;
+                }
+                for (int k = 0; k < m; k++) { /* H <- G^T H (rows a, b) */
+                    double x = H[a * m + k], y = H[b * m + k];
+                    H[a * m + k] = cs * x - sn * y;
+                    H[b * m + k] = sn * x + cs * y;
+                }
+                for (int k = 0; k < m; k++) { /* Y <- Y G */
+                    double x = Y[a * m + k], y = Y[b * m + k];
+                    Y[a * m + k] = cs * x - sn * y;
+                    Y[b * m + k] = sn * x + cs * y;
+                }
+            }
+    }
+    for (int i = 0; i < m; i++) ev[i] = H[i * m + i];
+    /* ascending order (insertion sort of the pairs) */
+    for (int a = 1; a < m; a++)
+        for (int b = a; b > 0 && ev[b] < ev[b - 1]; b--) {
+            double t = ev[b]; ev[b] = ev[b - 1]; ev[b - 1] = t;
+            for (int k = 0; k < m; k++) {
+                double y = Y[b * m + k]; Y[b * m + k] = Y[(b - 1) * m + k]; Y[(b - 1) * m + k] = y;
+            }
+        }
+}
+
+/*
+ * Jacobi-Davidson for eigenpair j (Sec. 6; readings in the design notes): the
+ * search space V (orthonormal, orthogonal to v_1..v_{j-1}) starts from x0;
+ * each step takes the Ritz pair (theta, u) of the smallest Ritz value from
+ * H = V^T A V, tests ||A u - theta u|| <= tau theta, restarts V with the m_min
+ * smallest Ritz vectors when it holds m_max vectors, and expands V with the
+ * correction s of J s = -r from the PCG of Sec. 4.3 (with the BFGS pairs of
+ * the correction solves when kmax > 0).  When the PCG takes no step (J is
+ * indefinite far from the eigenvalue) the space grows by its first
+ * preconditioned direction instead.  The Ritz vector is left in
+ * Qm + j n; returns the number of outer steps.
+ */
+static int jd_pair(const prob *P, const or_opts *o, int j, double *Qm, const double *x0, pairs_t *W, or_stats *st,
+                   double *theta_out, double *rn_out, double *work, double *Au, double *r, double *s, double *trace,
+                   int trace_cap) {
+    int n = P->n;
+    size_t N = (size_t)n;
+    int mmax = o->jd_mmax, mmin = o->jd_mmin;
+    double *V = malloc(sizeof(double) * N * mmax), *AV = malloc(sizeof(double) * N * mmax);
+    double *T2 = malloc(sizeof(double) * N * mmax);
+    double *t = malloc(sizeof(double) * N);
+    double *H = calloc((size_t)mmax * mmax, sizeof(double)), *Hw = malloc(sizeof(double) * mmax * mmax);
+    double *Y = malloc(sizeof(double) * mmax * mmax), ev[64], z[OR_MAXP + 64];
+    double *u = Qm + (size_t)j * N;
+    double theta = 0.0, rn = 0.0;
+    int m = 0, k = 0;
+    W->k = 0;
+    copy(n, x0, t);
+    for (;;) {
+        /* expand: t orthogonal to v_1..v_{j-1} and to V (classical Gram-Schmidt, twice), normalised */
+        for (int pass = 0; pass < 2; pass++) {
+            cgs(n, j, Qm, t, z);
+            cgs(n, m, V, t, z);
+        }
+        double tn = nrm2(n, t);
+        if (!(tn > 0.0)) break;
+        scal(n, 1.0 / tn, t);
+        copy(n, t, V + (size_t)m * N);
+        or_spmv(n, P->rp, P->ci, P->v, t, AV + (size_t)m * N);
+        st->mvp_newton++;
+        for (int i = 0; i <= m; i++) {
+            double h = dot(n, V + (size_t)i * N, AV + (size_t)m * N);
+            H[i * mmax + m] = h;
+            H[m * mmax + i] = h;
+        }
+        m++;
+        /* Rayleigh-Ritz: smallest Ritz pair of H */
+        for (int a = 0; a < m; a++)
+            for (int b = 0; b < m; b++) Hw[a * m + b] = H[a * mmax + b];
+        or_symeig(m, Hw, ev, Y);
+        theta = ev[0];
+        for (int i = 0; i < n; i++) { u[i] = 0.0; Au[i] = 0.0; }
+        for (int c = 0; c < m; c++) {
+            axpy(n, Y[c], V + (size_t)c * N, u);
+            axpy(n, Y[c], AV + (size_t)c * N, Au);
+        }
+        for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
+        rn = nrm2(n, r);
+        if (trace && st->ntrace < trace_cap) {
+            double *T = trace + 8 * (size_t)st->ntrace++;
+            T[0] = j; T[1] = k; T[2] = theta; T[3] = rn; T[4] = m; T[5] = ev[m > 1 ? 1 : 0]; T[6] = 0.0; T[7] = 0.0;
+        }
+        if (rn <= o->tol * theta || k >= o->itmax) break;
+        if (m == mmax) { /* thick restart with the m_min smallest Ritz vectors */
+            for (int c = 0; c < mmin; c++) {
+                double *tc = T2 + (size_t)c * N;
+                for (int i = 0; i < n; i++) tc[i] = 0.0;
+                for (int a = 0; a < m; a++) axpy(n, Y[c * m + a], V + (size_t)a * N, tc);
+            }
+            memcpy(V, T2, sizeof(double) * N * mmin);
+            for (int c = 0; c < mmin; c++) {
+                double *tc = T2 + (size_t)c * N;
+                for (int i = 0; i < n; i++) tc[i] = 0.0;
+                for (int a = 0; a < m; a++) axpy(n, Y[c * m + a], AV + (size_t)a * N, tc);
+            }
+            memcpy(AV, T2, sizeof(double) * N * mmin);
+            for (int a = 0; a < mmax * mmax; a++) H[a] = 0.0;
+            for (int c = 0; c < mmin; c++) H[c * mmax + c] = ev[c];
+            m = mmin;
+        }
+        /* correction equation, Sec. 4.3 PCG with the same exit tests */
+        int its = 0;
+        int why = or_pcg(P, theta, j + 1, Qm, u, Au, r, W->k, W->S, W->R, W->alpha, o->tol_pcg, o->itmax_pcg,
+                         o->tol, o->exit_rule, o->exit_xi, s, &its, work);
+        if (why == PCG_EXIT_BREAKDOWN) st->pcg_breakdowns++;
+        st->pcg_its[j] += its;
+        st->mvp_newton += its;
+        if (its > 0) {
+            double alpha = dot(n, s, r), sn2 = dot(n, s, s);
+            if (alpha < -1e-12 * sqrt(sn2) * rn) pairs_push(W, s, r, alpha);
+            else st->bfgs_skipped++;
+            copy(n, s, t);
+        } else {
+            copy(n, work + 2 * N, t); /* the PCG's first direction: preconditioned projected residual */
+        }
+        k++;
+    }
+    free(V); free(AV); free(T2); free(t); free(H); free(Hw); free(Y);
+    *theta_out = theta;
+    *rn_out = rn;
+    return k;
+}
+
+/*
  * Alg. 2 (DACG-Newton).  A in CSR (both triangles), x0 = p x n starting block
  * (row j for eigenpair j+1).  Outputs evals[p] ascending and evecs (p x n,
  * row j = v_{j+1}) with the first entry above 1e-12 ||v||_inf made positive.
  * trace (optional, trace_cap records of 8 doubles) receives per outer step:
- *   j, k, theta_k, ||r_k||, alpha_k = s_k^T r_k, ||s_k||^2, theta_{k+1}, PCG its.
+ *   j, k, theta_k, ||r_k||, alpha_k = s_k^T r_k, ||s_k||^2, theta_{k+1}, PCG its;
+ *   with jd = 1, per Rayleigh-Ritz step: j, k, theta, ||r||, dim V, second Ritz value, 0, 0.
  * Returns 0 when every pair converged, 1 if some did not, <0 on errors.
  */
 int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts *o,
@@ -621,8 +781,20 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
     double z[OR_MAXP + 1];
     int allconv = 1;
 
+    if (o->jd && (o->jd_mmin < 1 || o->jd_mmax <= o->jd_mmin || o->jd_mmax > 60)) return -1;
     for (int j = 0; j < p; j++) {
         double *u = Qm + (size_t)j * N; /* becomes v_{j+1} */
+        if (o->jd) {
+            double tn = now_s(), th, rnj;
+            st->outer_its[j] = jd_pair(&P, o, j, Qm, x0 + (size_t)j * N, &W, st, &th, &rnj, work, Au, r, s, trace,
+                                       trace_cap);
+            st->relres[j] = rnj / th;
+            st->converged[j] = (rnj <= o->tol * th);
+            if (!st->converged[j]) allconv = 0;
+            lam[j] = th;
+            st->t_newton += now_s() - tn;
+            continue;
+        }
         double td = now_s();
         /* DACG to tau_DACG before Newton, or to the final tau when it runs alone */
         st->dacg_its[j] = or_dacg(&P, j, Qm, x0 + (size_t)j * N, o->newton ? o->tol_dacg : o->tol, o->itmax_dacg, u,

@@ -651,3 +651,54 @@ def test_solve_with_ict_preconditioner(oracle_lib):
         ev1, V1, st1, _ = oracle_lib.solve(B, 4, ict=1, lfil=lf, tau_ic=tau)
         np.testing.assert_allclose(ev1, ev0, rtol=1e-10)
         _check_pairs(B, ev1, V1)
+
+
+# ----------------------------------------------------------------------------- Jacobi-Davidson (Sec. 6)
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 10, 16])
+def test_symeig_matches_numpy(oracle_lib, m):
+    """The Rayleigh-Ritz eigensolver (cyclic Jacobi) against numpy.linalg.eigh, and on a matrix with a
+    repeated eigenvalue through H Y = Y diag(ev) and Y^T Y = I."""
+    rng = np.random.default_rng(m)
+    M = rng.standard_normal((m, m))
+    H = M + M.T
+    ev, Y = oracle_lib.symeig(H)
+    np.testing.assert_allclose(ev, np.linalg.eigh(H)[0], rtol=0, atol=1e-13 * np.abs(H).max())
+    assert np.abs(H @ Y - Y * ev).max() <= 1e-13 * np.abs(H).max()
+    assert np.abs(Y.T @ Y - np.eye(m)).max() <= 1e-13
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    d = np.repeat([1.0, 2.0, 5.0], m)[:m]
+    H2 = Q @ np.diag(d) @ Q.T
+    ev2, Y2 = oracle_lib.symeig(H2)
+    np.testing.assert_allclose(ev2, np.sort(d), atol=1e-13)
+    assert np.abs(H2 @ Y2 - Y2 * ev2).max() <= 1e-13
+    assert np.abs(Y2.T @ Y2 - np.eye(m)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("kmax", [0, 5])
+def test_jd_closed_form_and_dense(oracle_lib, kmax):
+    """Jacobi-Davidson with the PCG correction solver (kmax = 0: the paper's JD with the fixed projected IC
+    preconditioner; kmax = 5: with the BFGS pairs): closed-form Laplacian eigenvalues and dense eigh."""
+    A, p = W.config_small()
+    ev, Vr, st, _ = oracle_lib.solve(A, p, jd=1, kmax=kmax)
+    np.testing.assert_allclose(ev, W.laplacian_2d_eigs(32)[:p], rtol=1e-10)
+    _check_pairs(A, ev, Vr)
+    assert st["status"] == 0 and sum(st["dacg_its"]) == 0
+    for B, q in ((W.diffusion_3d(8, seed=1), 5), (W.elasticity_q1(3, seed=2), 4), (W.laplacian_2d(20), 6)):
+        ev, Vr, st, _ = oracle_lib.solve(B, q, jd=1, kmax=kmax)
+        np.testing.assert_allclose(ev, np.linalg.eigh(dense(B))[0][:q], rtol=1e-10)
+        _check_pairs(B, ev, Vr)
+
+
+def test_jd_ritz_values_decrease_through_restarts(oracle_lib):
+    """Rayleigh-Ritz on nested subspaces: the smallest Ritz value never increases, and a thick restart keeps
+    it (m_min = 2, m_max = 4 forces many restarts); the space never exceeds m_max."""
+    B = W.diffusion_3d(10, seed=1)
+    ev, Vr, st, tr = oracle_lib.solve(B, 3, jd=1, jd_mmin=2, jd_mmax=4, trace_cap=4000)
+    np.testing.assert_allclose(ev, np.linalg.eigh(dense(B))[0][:3], rtol=1e-10)
+    assert tr[:, 4].max() <= 4 and (tr[:, 4] == 4).sum() > 3
+    for j in range(3):
+        th = tr[tr[:, 0] == j, 2]
+        assert len(th) > 5
+        assert np.all(np.diff(th) <= 1e-12 * th[0])
+    with pytest.raises(RuntimeError):
+        oracle_lib.solve(B, 2, jd=1, jd_mmin=4, jd_mmax=4)
