@@ -118,6 +118,10 @@ def main():
     ap.add_argument("--bfgs-full", type=int, default=0,
                     help="1: store the pairs of the full BFGS update eq. (2.1), y_k = r_{k+1} - r_k; 0: the "
                          "simplified update eq. (2.2) (default)")
+    ap.add_argument("--jd", type=int, default=0,
+                    help="1: Jacobi-Davidson outer iteration (Sec. 6, m_min 5, m_max 10) with the same PCG as "
+                         "correction solver, instead of DACG-Newton")
+    ap.add_argument("--kmax", type=int, default=5, help="BFGS window (0: the fixed initial preconditioner)")
     ap.add_argument("--ict", type=str, default="",
                     help="'LFIL,TAU': precondition with IC(lfil, tau_IC) instead of IC(0) (the paper's own initial "
                          "preconditioner; Table 2 defaults are 30,1e-2)")
@@ -168,7 +172,8 @@ def main():
     for name, prec in (("mixed", bnx.MIXED), ("fp64", bnx.FP64)):
         for w in range(args.warmup):
             S.factor(**fkw)
-            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
+                                 kmax=args.kmax)
             print(f"[bench] warmup {name} {w}: {st['t_dacg'] + st['t_newton']:.3f}s status {st['status']}",
                   flush=True)
         bnx.bnx_set_profiling(S.h, 1)
@@ -177,7 +182,8 @@ def main():
         stats = []
         for k in range(args.steps):
             S.factor(**fkw)
-            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full)
+            ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
+                                 kmax=args.kmax)
             stats.append(st)
             print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
                   flush=True)
@@ -254,7 +260,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"diffusion3d_{N}^3_lognormal_seed1", "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
                    "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
-                   "method": "DACG-Newton" if args.newton else "DACG alone",
+                   "method": ("Jacobi-Davidson" if args.jd else "DACG-Newton" if args.newton else "DACG alone"),
+                   "kmax": args.kmax,
                    "preconditioner": f"IC({args.ict})" if args.ict else "IC(0)",
                    "bfgs_update": "eq. (2.1) full" if args.bfgs_full else "eq. (2.2) simplified",
                    "fill_sigma": round(mixed["stats"]["fill"], 4)},

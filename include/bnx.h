@@ -77,6 +77,16 @@ typedef struct {
     int bfgs_full;      /* 0: pairs (s_k, r_k) of the simplified update eq. (2.2), y_k ~ -r_k;
                            1: y_k = r_{k+1} - r_k of eq. (2.1), stored as (s_k, r_k - r_{k+1}) and
                            skipped unless s_k^T y_k > 0                                  (0) */
+    int jd;             /* 1: Jacobi-Davidson outer iteration (Sec. 6) instead of DACG + Newton:
+                           per eigenpair a search space V starts from the start vector (no
+                           DACG), Rayleigh-Ritz on V^T A V gives the smallest Ritz pair, the
+                           outer test is the one of Alg. 2, V restarts with the jd_mmin smallest
+                           Ritz vectors when it holds jd_mmax, and it grows by the correction of
+                           the same PCG (same exit tests; the BFGS pairs of the previous
+                           correction solves when kmax > 0, the paper's JD when kmax = 0).
+                           newton is ignored; dacg_its stay 0; outer_its count corrections  (0) */
+    int jd_mmin;        /* (5, Sec. 6); >= 1 */
+    int jd_mmax;        /* (10, Sec. 6); jd_mmin < jd_mmax <= 16 */
 } bnx_solve_opts;
 
 /* Initial preconditioner P0^ = (L L^T)^{-1} of Sec. 2.  Breakdown policy: on a

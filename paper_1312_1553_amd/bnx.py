@@ -30,7 +30,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("p", C.c_int), ("tol", C.c_double), ("itmax", C.c_int), ("tol_dacg", C.c_double),
                 ("itmax_dacg", C.c_int), ("tol_pcg", C.c_double), ("itmax_pcg", C.c_int), ("kmax", C.c_int),
                 ("precision", C.c_int), ("exit_rule", C.c_int), ("exit_xi", C.c_double), ("seed", C.c_uint64),
-                ("x0", C.c_void_p), ("keep_bfgs", C.c_int), ("newton", C.c_int), ("bfgs_full", C.c_int)]
+                ("x0", C.c_void_p), ("keep_bfgs", C.c_int), ("newton", C.c_int), ("bfgs_full", C.c_int),
+                ("jd", C.c_int), ("jd_mmin", C.c_int), ("jd_mmax", C.c_int)]
 
 
 class FactorOpts(C.Structure):

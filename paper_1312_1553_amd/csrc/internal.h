@@ -12,6 +12,7 @@ constexpr int kMaxP = 32;      // eigenpairs per solve
 constexpr int kMaxK = 16;      // BFGS window
 constexpr int kMaxQ = kMaxP + 1;
 constexpr int kMaxVec = 80;    // vectors in one kernel argument list
+constexpr int kJdMax = 16;     // largest Jacobi-Davidson search space
 #ifndef BNX_NBMAX
 #define BNX_NBMAX 2048
 #endif
@@ -44,6 +45,9 @@ struct DevCtl {
   // outer step (always double)
   double oz[kMaxQ], onrm2, otheta, orn, oalpha, osn2, ornold;
   double oya, oyn2;  // s^T (r_k - r_{k+1}) and ||r_k - r_{k+1}||^2 for the full BFGS pair
+  // Jacobi-Davidson search space (Sec. 6): H = V^T A V (row-major), Ritz values ascending, Ritz
+  // vectors of H (vector c at jY[c*kJdMax ...], the coefficients of the c-th Ritz vector in V)
+  double jH[kJdMax * kJdMax], jY[kJdMax * kJdMax], jev[kJdMax];
   // backward
   double bz[kMaxQ];
   int err;  // bounded wait exceeded somewhere

@@ -517,6 +517,87 @@ __global__ void c_outer_y(DevCtl *c, const double *part, int nb) {
   c->oyn2 = red[1];
 }
 
+// ------------------------------------------------------------------ Jacobi-Davidson (Sec. 6)
+// new column m of H = V^T A V from the dots v_i^T (A v_m), i <= m (mirrored into row m)
+__global__ void c_jd_col(DevCtl *c, const double *part, int nb, int m) {
+  __shared__ double red[kJdMax];
+  reduce_parts(part, nb, m + 1, red);
+  if (threadIdx.x) return;
+  for (int i = 0; i <= m; i++) {
+    c->jH[i * kJdMax + m] = red[i];
+    c->jH[m * kJdMax + i] = red[i];
+  }
+}
+
+// Rayleigh-Ritz on the m x m matrix H: Jacobi rotations, each zeroing one off-diagonal
+// entry of a working copy, sweep after sweep until the off-diagonal mass is negligible;
+// the rotations accumulate in E (eigenvectors as columns).  Ritz values go to jev in
+// ascending order with their vectors in jY; theta = the smallest.  One thread: m <= 16.
+__global__ void c_jd_rr(DevCtl *c, int m) {
+  __shared__ double a[kJdMax][kJdMax], E[kJdMax][kJdMax];
+  __shared__ int ord[kJdMax];
+  if (threadIdx.x) return;
+  for (int i = 0; i < m; i++)
+    for (int q = 0; q < m; q++) {
+      a[i][q] = c->jH[i * kJdMax + q];
+      E[i][q] = i == q ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 64; sweep++) {
+    double off = 0.0, all = 0.0;
+    for (int i = 0; i < m; i++)
+      for (int q = 0; q < m; q++) {
+        const double x = a[i][q] * a[i][q];
+        all += x;
+        if (i != q) off += x;
+      }
+    if (!(off > 1e-30 * all)) break;
+    for (int pp = 0; pp + 1 < m; pp++)
+      for (int qq = pp + 1; qq < m; qq++) {
+        const double apq = a[pp][qq];
+        if (apq == 0.0) continue;
+        const double w = (a[qq][qq] - a[pp][pp]) / (2.0 * apq);
+        const double t = (w < 0.0 ? -1.0 : 1.0) / (fabs(w) + sqrt(w * w + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int i = 0; i < m; i++) {  // columns pp, qq
+          const double x = a[i][pp], y = a[i][qq];
+          a[i][pp] = cs * x - sn * y;
+          a[i][qq] = sn * x + cs * y;
+        }
+        for (int i = 0; i < m; i++) {  // rows pp, qq
+          const double x = a[pp][i], y = a[qq][i];
+          a[pp][i] = cs * x - sn * y;
+          a[qq][i] = sn * x + cs * y;
+        }
+        for (int i = 0; i < m; i++) {
+          const double x = E[i][pp], y = E[i][qq];
+          E[i][pp] = cs * x - sn * y;
+          E[i][qq] = sn * x + cs * y;
+        }
+      }
+  }
+  for (int i = 0; i < m; i++) ord[i] = i;
+  for (int i = 0; i < m; i++) {  // selection of the ascending order
+    int best = i;
+    for (int q = i + 1; q < m; q++)
+      if (a[ord[q]][ord[q]] < a[ord[best]][ord[best]]) best = q;
+    const int tmp = ord[i];
+    ord[i] = ord[best];
+    ord[best] = tmp;
+  }
+  for (int cc = 0; cc < m; cc++) {
+    c->jev[cc] = a[ord[cc]][ord[cc]];
+    for (int i = 0; i < m; i++) c->jY[cc * kJdMax + i] = E[i][ord[cc]];
+  }
+  c->otheta = c->jev[0];
+}
+
+// after a thick restart with the mmin smallest Ritz vectors, H is their Ritz values
+__global__ void c_jd_restart(DevCtl *c, int mmin) {
+  if (threadIdx.x) return;
+  for (int i = 0; i < kJdMax; i++)
+    for (int q = 0; q < kJdMax; q++) c->jH[i * kJdMax + q] = (i == q && i < mmin) ? c->jev[i] : 0.0;
+}
+
 // Gram blocks from scratch, rows row0..row0+nrows-1 of M (kind 0, s_s^T r_t) or of Q^T S (kind 1)
 __global__ void c_gram_rows(DevCtl *c, const double *part, int nb, int k, int kind, int row0, int nrows) {
   __shared__ double red[kPartSlots];
@@ -1398,6 +1479,192 @@ __global__ void k_splitmix(size_t count, uint64_t seed, double *out) {
 }
 
 // ------------------------------------------------------------------ full solve (Alg. 2)
+// x <- x - Q (Q^T x): one classical Gram-Schmidt pass (double)
+void cgs_pass(bnx_ctx *C, double *x, double *tmp, int nq, const VList<double> &Q) {
+  if (nq == 0) return;
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  VList<double> X{}, Y{};
+  for (int q = 0; q < nq; q++) {
+    X.p[q] = Q.p[q];
+    Y.p[q] = x;
+  }
+  const int nb = launch_multidot<double, double>(L, C->n, nq, X, Y, area(L, 4), nullptr);
+  hipLaunchKernelGGL(c_outer_cgs, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb, nq, 0);
+  comb<double>(C, tmp, x, 1.0, nullptr, nullptr, nullptr, nq, Q, c->oz, -1.0, 0, VList<double>{}, nullptr, nullptr);
+  HIPCHK(hipMemcpyAsync(x, tmp, sizeof(double) * C->n, hipMemcpyDeviceToDevice, C->st));
+}
+
+// Jacobi-Davidson for eigenpair j (Sec. 6).  The search space V (orthonormal, orthogonal to the
+// converged vectors Qt, at most mmax vectors; AV = A V kept beside it) starts from t.  Each step:
+// expand V by t (classical Gram-Schmidt against Qt and V, twice), Rayleigh-Ritz on H = V^T A V,
+// the smallest Ritz pair (theta, u) and r = A u - theta u, the outer test ||r|| <= tau theta, a
+// thick restart with the mmin smallest Ritz vectors when V is full, then the correction s of
+// J s = -r by the PCG of Sec. 4.3 with the BFGS pairs of the previous correction solves (kmax > 0).
+// When the PCG takes no step (J indefinite far from the eigenvalue), V grows by the PCG's first
+// preconditioned direction instead.  Leaves u, Au, r (double) of the last Ritz pair.
+template <typename T>
+void jd_pair(bnx_ctx *C, const bnx_solve_opts &o, Work<T> &w, int j, const VList<double> &Qt64, const VList<T> &QtT,
+             double *t, double *u, double *Au, double *r, double *tmp, double *V, double *AV, double *Vt,
+             bnx_stats &S, double &theta, double &rn, int &k) {
+  const int n = C->n;
+  const Launch L = C->launch();
+  DevCtl *c = C->ctl;
+  const bool fp64 = std::is_same<T, double>::value;
+  const int mmax = o.jd_mmax, mmin = o.jd_mmin;
+  Mat<double> A = C->mat<double>();
+  T *uT = fp64 ? (T *)u : w.u, *AuT = fp64 ? (T *)Au : w.Au, *rT = fp64 ? (T *)r : w.r;
+  std::deque<int> ring;
+  bool inserted = false;
+  int shift = 0, m = 0;
+  k = 0;
+  theta = rn = 0.0;
+  for (;;) {
+    // ---- expand V
+    VList<double> VL{}, AVL{};
+    for (int i = 0; i < m; i++) {
+      VL.p[i] = V + (size_t)i * n;
+      AVL.p[i] = AV + (size_t)i * n;
+    }
+    for (int pass = 0; pass < 2; pass++) {
+      cgs_pass(C, t, tmp, j, Qt64);
+      cgs_pass(C, t, tmp, m, VL);
+    }
+    VList<double> TT = vl<double>({t});
+    int nb = launch_multidot<double, double>(L, n, 1, TT, TT, area(L, 4), nullptr);
+    hipLaunchKernelGGL(c_outer_cgs, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb, 0, 1);
+    if (!(C->readctl().onrm2 > 0.0)) break;  // nothing left to add
+    hipLaunchKernelGGL(c_inv_sqrt, dim3(1), dim3(1), 0, C->st, c, &c->onrm2, &c->dinv);
+    double *vm = V + (size_t)m * n, *avm = AV + (size_t)m * n;
+    comb<double>(C, vm, t, 1.0, &c->dinv, nullptr, nullptr, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                 nullptr, nullptr);
+    launch_spmv<double>(L, A, vm, avm, 0, VList<double>{}, 0, VList<double>{}, area(L, 5), nullptr);
+    S.mvp_newton++;
+    VL.p[m] = vm;
+    AVL.p[m] = avm;
+    VList<double> Y{};
+    for (int i = 0; i <= m; i++) Y.p[i] = avm;
+    nb = launch_multidot<double, double>(L, n, m + 1, VL, Y, area(L, 4), nullptr);
+    hipLaunchKernelGGL(c_jd_col, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb, m);
+    m++;
+    // ---- Rayleigh-Ritz: u = V y, A u = AV y for the smallest Ritz value, r = A u - theta u
+    hipLaunchKernelGGL(c_jd_rr, dim3(1), dim3(64), 0, C->st, c, m);
+    comb<double>(C, u, nullptr, 0.0, nullptr, nullptr, nullptr, m, VL, c->jY, 1.0, 0, VList<double>{}, nullptr,
+                 nullptr);
+    comb<double>(C, Au, nullptr, 0.0, nullptr, nullptr, nullptr, m, AVL, c->jY, 1.0, 0, VList<double>{}, nullptr,
+                 nullptr);
+    const int nbi = gridn(n);
+    hipLaunchKernelGGL((k_outer_resid<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, r, fp64 ? nullptr : w.u,
+                       fp64 ? nullptr : w.Au, fp64 ? nullptr : w.r, area(L, 5));
+    hipLaunchKernelGGL(c_outer_rn, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
+    // ---- Gram blocks of the pairs for this u (and for the pair stored after the last correction)
+    const int kn = (int)ring.size();
+    if (kn > 0) {
+      VList<T> X{}, Yg{};
+      int D = 0;
+      if (inserted) {
+        const T *snew = w.S[ring.back()], *rnew = w.R[ring.back()];
+        for (int q = 0; q < kn; q++) {
+          X.p[D] = snew;
+          Yg.p[D++] = w.R[ring[q]];
+        }
+        for (int q = 0; q < kn - 1; q++) {
+          X.p[D] = w.S[ring[q]];
+          Yg.p[D++] = rnew;
+        }
+        for (int q = 0; q < j; q++) {
+          X.p[D] = QtT.p[q];
+          Yg.p[D++] = snew;
+        }
+      }
+      for (int q = 0; q < kn; q++) {
+        X.p[D] = uT;
+        Yg.p[D++] = w.S[ring[q]];
+      }
+      const int nbg = launch_multidot<T, double>(L, n, D, X, Yg, area(L, 6), nullptr);
+      hipLaunchKernelGGL(c_gram, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 6), nbg, shift, inserted ? 1 : 0, kn,
+                         j);
+    }
+    inserted = false;
+    shift = 0;
+    const DevCtl h = C->readctl();
+    theta = h.otheta;
+    rn = h.orn;
+    if (rn <= o.tol * theta || k >= o.itmax) break;
+    if (m == mmax) {  // thick restart: the mmin smallest Ritz vectors (u is the first)
+      for (int cc = 0; cc < mmin; cc++)
+        comb<double>(C, Vt + (size_t)cc * n, nullptr, 0.0, nullptr, nullptr, nullptr, m, VL, c->jY + cc * kJdMax,
+                     1.0, 0, VList<double>{}, nullptr, nullptr);
+      HIPCHK(hipMemcpyAsync(V, Vt, sizeof(double) * n * mmin, hipMemcpyDeviceToDevice, C->st));
+      for (int cc = 0; cc < mmin; cc++)
+        comb<double>(C, Vt + (size_t)cc * n, nullptr, 0.0, nullptr, nullptr, nullptr, m, AVL, c->jY + cc * kJdMax,
+                     1.0, 0, VList<double>{}, nullptr, nullptr);
+      HIPCHK(hipMemcpyAsync(AV, Vt, sizeof(double) * n * mmin, hipMemcpyDeviceToDevice, C->st));
+      hipLaunchKernelGGL(c_jd_restart, dim3(1), dim3(64), 0, C->st, c, mmin);
+      m = mmin;
+    }
+    // ---- correction equation
+    VList<T> Q = QtT;
+    Q.p[j] = uT;
+    VList<T> AQ{};
+    for (int q = 0; q < j; q++) AQ.p[q] = w.AQm + (size_t)q * n;
+    AQ.p[j] = AuT;
+    VList<T> SL{}, RL{};
+    for (size_t q = 0; q < ring.size(); q++) {
+      SL.p[q] = w.S[ring[q]];
+      RL.p[q] = w.R[ring[q]];
+    }
+    PcgParams P;
+    P.theta = theta;
+    P.tol_pcg = o.tol_pcg;
+    P.itmax = o.itmax_pcg;
+    P.tau = o.tol;
+    P.exit_rule = o.exit_rule;
+    P.xi = o.exit_xi;
+    P.sgn = -1.0;
+    P.eigtest = 1;
+    int its = 0, why = 0;
+    pcg<T>(C, w, P, rT, j + 1, Q, AQ, (int)ring.size(), SL, RL, uT, AuT, w.s, &its, &why);
+    S.pcg_its[j] += its;
+    S.mvp_newton += its;
+    if (why == 4) S.pcg_breakdowns++;
+    if (its > 0) {
+      // the pair (s_k, r_k) of Alg. 2, stored unless s^T r >= -1e-12 ||s|| ||r||
+      VList<T> X{}, Yd{};
+      X.p[0] = w.s;
+      Yd.p[0] = rT;
+      X.p[1] = w.s;
+      Yd.p[1] = w.s;
+      const int nb2 = launch_multidot<T, double>(L, n, 2, X, Yd, area(L, 4), nullptr);
+      hipLaunchKernelGGL(c_outer_y, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nb2);
+      const DevCtl hy = C->readctl();
+      if (o.kmax > 0 && hy.oya < -1e-12 * std::sqrt(hy.oyn2) * rn) {
+        int slot;
+        if ((int)ring.size() == o.kmax) {
+          slot = ring.front();
+          ring.pop_front();
+          shift = 1;
+        } else {
+          std::vector<bool> used(o.kmax, false);
+          for (int q : ring) used[q] = true;
+          slot = 0;
+          while (used[slot]) slot++;
+        }
+        HIPCHK(hipMemcpyAsync(w.S[slot], w.s, sizeof(T) * n, hipMemcpyDeviceToDevice, C->st));
+        launch_cast<double, T>(C->st, n, r, w.R[slot]);
+        ring.push_back(slot);
+        inserted = true;
+      } else {
+        S.bfgs_skipped++;
+      }
+      launch_cast<T, double>(C->st, n, w.s, t);
+    } else {
+      launch_cast<T, double>(C->st, n, w.p, t);  // the first preconditioned direction
+    }
+    k++;
+  }
+}
+
 template <typename T>
 bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double *evecs, bnx_stats *st) {
   const int n = C->n, p = o.p;
@@ -1426,6 +1693,12 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
   double *V64 = dalloc((size_t)n * p);  // converged vectors v_1..v_p (unsorted)
   double *X0 = dalloc((size_t)n * p);
   double *u = dalloc(n), *Au = dalloc(n), *rA = dalloc(n), *rB = dalloc(n), *x64 = dalloc(n), *tmp = dalloc(n);
+  double *Vjd = nullptr, *AVjd = nullptr, *Vtjd = nullptr;  // Jacobi-Davidson search space
+  if (o.jd) {
+    Vjd = dalloc((size_t)n * o.jd_mmax);
+    AVjd = dalloc((size_t)n * o.jd_mmax);
+    Vtjd = dalloc((size_t)n * o.jd_mmin);
+  }
   if (o.x0) {
     HIPCHK(hipMemcpyAsync(X0, o.x0, sizeof(double) * n * p, C->device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           C->st));
@@ -1446,6 +1719,22 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     }
     HIPCHK(hipMemcpyAsync(x64, X0 + (size_t)j * n, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
     cgs2_normalize(C, x64, tmp, j, Qt64);
+    if (o.jd) {  // Jacobi-Davidson from the start vector, no DACG (Sec. 6)
+      t0 = now_s();
+      double theta_j = 0.0, rn_j = 0.0;
+      int k_j = 0;
+      jd_pair<T>(C, o, w, j, Qt64, QtT, x64, u, Au, rA, tmp, Vjd, AVjd, Vtjd, S, theta_j, rn_j, k_j);
+      S.outer_its[j] = k_j;
+      S.relres[j] = rn_j / theta_j;
+      S.converged[j] = rn_j <= o.tol * theta_j;
+      lam[j] = theta_j;
+      HIPCHK(hipMemcpyAsync(V64 + (size_t)j * n, u, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+      if (!fp64) launch_cast<double, T>(C->st, n, u, w.Qm + (size_t)j * n);
+      launch_cast<double, T>(C->st, n, Au, w.AQm + (size_t)j * n);
+      C->sync();
+      S.t_newton += now_s() - t0;
+      continue;
+    }
     launch_cast<double, T>(C->st, n, x64, w.x);
     long long mvp = 0;
     // DACG to tau_DACG before Newton; alone, to the final tau, and then always in double (tau is far
@@ -2253,6 +2542,9 @@ void bnx_default_solve_opts(bnx_solve_opts *o) {
   o->keep_bfgs = 0;
   o->newton = 1;
   o->bfgs_full = 0;
+  o->jd = 0;
+  o->jd_mmin = 5;
+  o->jd_mmax = 10;
 }
 
 void bnx_default_factor_opts(bnx_factor_opts *o) {
@@ -2403,6 +2695,8 @@ bnx_status bnx_solve(bnx_ctx *C, const bnx_solve_opts *opts, double *evals, doub
     if (o.kmax < 0 || o.kmax > BNX_MAX_KMAX) throw ApiError{BNX_E_ARG, "kmax out of range"};
     if (!prec_ok(o.precision)) throw ApiError{BNX_E_ARG, "unknown precision"};
     if (o.itmax < 0 || o.itmax_pcg < 1 || o.itmax_dacg < 0 || !(o.tol > 0)) throw ApiError{BNX_E_ARG, "bad iteration parameters"};
+    if (o.jd && (o.jd_mmin < 1 || o.jd_mmax <= o.jd_mmin || o.jd_mmax > kJdMax))
+      throw ApiError{BNX_E_ARG, "Jacobi-Davidson needs 1 <= jd_mmin < jd_mmax <= 16"};
     if (o.precision == BNX_FP64) return solve_impl<double>(C, o, evals, evecs, stats);
     return solve_impl<float>(C, o, evals, evecs, stats);
   });

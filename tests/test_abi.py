@@ -54,6 +54,7 @@ int main(void) {
          offsetof(bnx_stats, t_newton));
   printf("%zu %zu %zu %zu %zu\n", sizeof(bnx_factor_opts), offsetof(bnx_factor_opts, lfil),
          offsetof(bnx_factor_opts, tau_ic), offsetof(bnx_stats, nnz_L), offsetof(bnx_stats, fill));
+  printf("%zu %zu\n", offsetof(bnx_solve_opts, jd), offsetof(bnx_solve_opts, jd_mmax));
   return 0;
 }
 '''
@@ -67,7 +68,8 @@ int main(void) {
     S, T = bnx.SolveOpts, bnx.Stats
     want = [ctypes.sizeof(S), S.seed.offset, S.x0.offset, S.keep_bfgs.offset, S.newton.offset, S.bfgs_full.offset,
             ctypes.sizeof(T), T.mvp_dacg.offset, T.t_newton.offset, ctypes.sizeof(bnx.FactorOpts),
-            bnx.FactorOpts.lfil.offset, bnx.FactorOpts.tau_ic.offset, T.nnz_L.offset, T.fill.offset]
+            bnx.FactorOpts.lfil.offset, bnx.FactorOpts.tau_ic.offset, T.nnz_L.offset, T.fill.offset,
+            S.jd.offset, S.jd_mmax.offset]
     assert got == want
 
 
@@ -79,6 +81,7 @@ def test_defaults_match_paper_table2(lib):
     assert o.tol == g["tau"] and o.itmax == g["itmax"] and o.tol_dacg == g["tau_dacg"]
     assert o.tol_pcg == g["tau_pcg"] and o.itmax_pcg == g["itmax_pcg"]
     assert o.kmax == 5 and o.precision == 0
+    assert o.jd == 0 and o.jd_mmin == 5 and o.jd_mmax == 10  # Sec. 6
     f = bnx.bnx_default_factor_opts()
     assert f.lfil == g["lfil"] and f.tau_ic == g["tau_ic"] and f.ict == 0
 

@@ -212,3 +212,31 @@ def test_fullsize_c1_ict_solves(oracle_mod):
         assert e64 < 1e-11, (which, e64)
         assert e32 < 1e-5, (which, e32)
     S.close()
+
+
+@pytest.mark.parametrize("kmax", [0, 5])
+def test_fullsize_c1_jd_matches_oracle_evals(kmax):
+    """Jacobi-Davidson (Sec. 6) on the full C1 problem, p = 10, fp64 and mixed: the same eigenvalues as the
+    oracle's DACG-Newton run stored in tests/golden (the eigenpairs do not depend on the outer method),
+    residuals by scipy, orthonormality."""
+    g = json.load(open(os.path.join(GOLDEN, "oracle_evals_diffusion3d_100_p10.json")))
+    p = g["p"]
+    A = W.diffusion_3d(100, seed=1)
+    S = bnx.Solver(A.rowptr, A.col, A.val)
+    S.factor()
+    x0 = torch.as_tensor(W.initial_block(A.n, p, 0)).cuda()
+    ref = np.array(g["evals"])
+    M = A.to_scipy()
+    for prec in (FP64, MIXED):
+        say("case fullsize C1 jd", kmax, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, jd=1, kmax=kmax)
+        ev = ev.numpy()
+        assert st["status"] == 0 and all(st["converged"][:p]) and sum(st["dacg_its"]) == 0
+        rel = np.abs(ev - ref) / ref
+        say("  max rel eigenvalue difference vs oracle", rel.max())
+        assert rel.max() < 1e-10
+        Vh = host(V)
+        for i in range(p):
+            assert np.linalg.norm(M @ Vh[i] - ev[i] * Vh[i]) <= 1.01e-8 * ev[i]
+        assert np.abs(Vh @ Vh.T - np.eye(p)).max() < 1e-10
+    S.close()

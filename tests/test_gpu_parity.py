@@ -538,3 +538,42 @@ def test_unsplit_long_rows(oracle_mod, name, fkw, monkeypatch):
         bnx.bnx_ic_apply(S.h, MIXED, which, dev(b), x)
         assert np.abs(host(x) - refs[which]).max() <= 1e-4 * np.abs(refs[which]).max()
     S.close()
+
+
+# ----------------------------------------------------------------------------- Jacobi-Davidson (Sec. 6)
+@pytest.mark.parametrize("name,p,kmax,kw", [("laplace2d_32", 4, 5, {}), ("laplace2d_32", 4, 0, {}),
+                                            ("diffusion_12", 6, 5, {}), ("elasticity_3", 4, 0, {}),
+                                            ("diffusion_12", 3, 5, {"jd_mmin": 2, "jd_mmax": 4})])
+def test_jd_matches_oracle(oracle_mod, name, p, kmax, kw):
+    """Jacobi-Davidson with the PCG correction solver (kmax = 0: fixed projected IC preconditioner, the
+    paper's JD; kmax = 5: with the BFGS pairs) against the oracle run with the same options: eigenvalues,
+    residuals, no DACG, and in fp64 the same outer and PCG iteration totals within 10 %; the last case
+    restarts the search space often."""
+    A = mats()[name]
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0, jd=1, kmax=kmax, **kw)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case jd", name, p, kmax, kw, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, jd=1, kmax=kmax, **kw)
+        ev = ev.numpy()
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, host(V), 1e-8)
+        assert st["status"] == 0 and sum(st["dacg_its"]) == 0
+        if prec == FP64:
+            for key in ("outer_its", "pcg_its"):
+                a, b = sum(st[key]), sum(st_o[key])
+                assert abs(a - b) <= 0.1 * b + 2, (key, a, b)
+    S.close()
+
+
+def test_jd_rejects_bad_space():
+    A = mats()["laplace2d_32"]
+    S = solver_for(A)
+    S.factor()
+    for mm in ((0, 4), (4, 4), (5, 17)):
+        with pytest.raises(bnx.BnxError) as ei:
+            S.solve(2, jd=1, jd_mmin=mm[0], jd_mmax=mm[1])
+        assert ei.value.code == -1
+    S.close()
