@@ -693,27 +693,21 @@ __global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
 }
 
 // after multi-dot (Qt^T c0 (nq), g^T c0): zQ, gamma, beta
+// dots, in order: Qt^T g (nq), Qt^T c0 (nq), g^T c0
 __global__ void c_dacg_beta(DevCtl *c, const double *part, int nb, int nq) {
   if (c->ddone) return;
-  __shared__ double red[kMaxQ + 1];
-  reduce_parts(part, nb, nq + 1, red);
+  __shared__ double red[2 * kMaxQ + 1];
+  reduce_parts(part, nb, 2 * nq + 1, red);
   if (threadIdx.x) return;
-  // gamma = g^T h with h = c0 - Qt zQ and g orthogonal to Qt up to rounding: g^T h = g^T c0 - (Qt^T g)^T zQ,
-  // the second term is formed from Qg (dots of g with Qt) stored by the previous multidot.
-  double gam = red[nq];
+  // gamma = g^T h with h = c0 - Qt zQ and g orthogonal to Qt up to rounding: g^T h = g^T c0 - (Qt^T g)^T zQ
+  double gam = red[2 * nq];
   for (int q = 0; q < nq; q++) {
-    c->zQ[q] = red[q];
-    gam -= red[q] * c->Qg[q];
+    c->Qg[q] = red[q];
+    c->zQ[q] = red[nq + q];
+    gam -= red[nq + q] * red[q];
   }
   c->beta = (c->dits == 0 || c->dgamma_prev == 0.0) ? 0.0 : gam / c->dgamma_prev;
   c->dgamma = gam;
-}
-
-__global__ void c_dacg_qg(DevCtl *c, const double *part, int nb, int nq) {
-  if (c->ddone) return;
-  __shared__ double red[kMaxQ];
-  reduce_parts(part, nb, nq, red);
-  if (threadIdx.x < nq) c->Qg[threadIdx.x] = red[threadIdx.x];
 }
 
 // after the d update (dots d^T Ax, d^T x, d^T d) and SpMV Ad = A d (dot d^T Ad)
@@ -1279,9 +1273,13 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
   const int nbi = gridn(n);
   const int Di = 1 + k + m;
   T *t = P.eigtest ? w.t : nullptr;
+  // accumulator count tiers: the widest one costs registers (and occupancy) a typical solve never uses
   if (Di <= 8)
     hipLaunchKernelGGL((k_pcg_init<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, P.sgn, r, m, Q, k, S, w.g, s_out,
                        t, area(L, 1));
+  else if (Di <= 24)
+    hipLaunchKernelGGL((k_pcg_init<T, 24>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, P.sgn, r, m, Q, k, S, w.g,
+                       s_out, t, area(L, 1));
   else
     hipLaunchKernelGGL((k_pcg_init<T, 1 + kMaxK + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, P.sgn, r, m, Q,
                        k, S, w.g, s_out, t, area(L, 1));
@@ -1314,6 +1312,9 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     if (2 * m <= 8)
       hipLaunchKernelGGL((k_pcg_newp<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
                          l > 0 ? 1 : 0, 2 * m, AQ, area(L, 8));
+    else if (2 * m <= 24)
+      hipLaunchKernelGGL((k_pcg_newp<T, 24>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
+                         l > 0 ? 1 : 0, 2 * m, AQ, area(L, 8));
     else
       hipLaunchKernelGGL((k_pcg_newp<T, 2 * kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
                          l > 0 ? 1 : 0, 2 * m, AQ, area(L, 8));
@@ -1323,6 +1324,9 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     if (Du <= 8)
       hipLaunchKernelGGL((k_pcg_update<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u, Au,
                          s_out, w.g, t, area(L, 1));
+    else if (Du <= 24)
+      hipLaunchKernelGGL((k_pcg_update<T, 24>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u,
+                         Au, s_out, w.g, t, area(L, 1));
     else
       hipLaunchKernelGGL((k_pcg_update<T, 3 + kMaxK + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m,
                          Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
@@ -1395,15 +1399,15 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   // Ax
   launch_spmv<T>(L, A, w.x, w.Ax, 0, VList<T>{}, 0, VList<T>{}, nullptr, nullptr);
   (*mvp)++;
-  VList<T> mdX{}, mdY{}, mdQg{}, mdQgY{};
+  VList<T> mdX{}, mdY{};  // one pass after the solves: Qt^T g, Qt^T c0, g^T c0
   for (int q = 0; q < nq; q++) {
     mdX.p[q] = Qt.p[q];
-    mdY.p[q] = w.c0;
-    mdQg.p[q] = Qt.p[q];
-    mdQgY.p[q] = w.dg;
+    mdY.p[q] = w.dg;
+    mdX.p[nq + q] = Qt.p[q];
+    mdY.p[nq + q] = w.c0;
   }
-  mdX.p[nq] = w.dg;
-  mdY.p[nq] = w.c0;
+  mdX.p[2 * nq] = w.dg;
+  mdY.p[2 * nq] = w.c0;
   VList<T> ly{}, lx{};
   ly.p[0] = w.d;
   lx.p[0] = w.Ax;
@@ -1420,11 +1424,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
-    if (nq > 0) {
-      int nbq = launch_multidot<T, T>(L, n, nq, mdQg, mdQgY, area(L, 2), gate);
-      hipLaunchKernelGGL(c_dacg_qg, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbq, nq);
-    }
-    int nbd = launch_multidot<T, T>(L, n, nq + 1, mdX, mdY, area(L, 3), gate);
+    int nbd = launch_multidot<T, T>(L, n, 2 * nq + 1, mdX, mdY, area(L, 3), gate);
     hipLaunchKernelGGL(c_dacg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd, nq);
     // d = -(c0 - Qt zQ) + beta d
     // (dots of the new d with Ax, x and d itself)
@@ -1799,6 +1799,9 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
       const int nbi = gridn(n);
       if (3 + j <= 8)
         hipLaunchKernelGGL((k_outer_add<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, u, w.s, r_old, x64, j, Qt64,
+                           area(L, 4));
+      else if (3 + j <= 16)
+        hipLaunchKernelGGL((k_outer_add<T, 16>), dim3(nbi), dim3(kBlock), 0, C->st, n, u, w.s, r_old, x64, j, Qt64,
                            area(L, 4));
       else
         hipLaunchKernelGGL((k_outer_add<T, 3 + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, u, w.s, r_old, x64, j,
