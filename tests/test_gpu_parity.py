@@ -577,3 +577,57 @@ def test_jd_rejects_bad_space():
             S.solve(2, jd=1, jd_mmin=mm[0], jd_mmax=mm[1])
         assert ei.value.code == -1
     S.close()
+
+
+# ----------------------------------------------------------------------------- edge cases
+def _tiny():
+    import scipy.sparse as sp
+    mats_ = {"1x1": np.array([[3.0]]), "2x2": np.array([[2.0, -1.0], [-1.0, 2.0]]),
+             "diag5": np.diag([5.0, 1.0, 3.0, 2.0, 4.0]), "lap3x3": W.laplacian_2d(3).to_scipy().toarray()}
+    return {k: (W._from_scipy(sp.csr_matrix(v)), v) for k, v in mats_.items()}
+
+
+@pytest.mark.parametrize("name", ["1x1", "2x2", "diag5", "lap3x3"])
+@pytest.mark.parametrize("kw", [{}, {"jd": 1}, {"newton": 0}])
+def test_tiny_matrices_all_pairs(oracle_mod, name, kw):
+    """Degenerate sizes: n from 1 to 9 (one partial 64-row slice, one block), p = 1 and p = n (the last
+    pair lives in a one-dimensional complement), for DACG-Newton, JD and DACG alone, fp64 and mixed;
+    eigenvalues against dense eigh and the oracle."""
+    A, D = _tiny()[name]
+    S = solver_for(A)
+    S.factor()
+    ref = np.linalg.eigh(D)[0]
+    for p in sorted({1, A.n}):
+        x0 = W.initial_block(A.n, p, 0)
+        ev_o, _, _, _ = oracle_mod.solve(A, p, x0=x0, **kw)
+        for prec in (FP64, MIXED):
+            say("case tiny", name, kw, p, prec)
+            ev, V, st = S.solve(p, precision=prec, x0=x0, **kw)
+            ev = ev.numpy()
+            np.testing.assert_allclose(ev, ref[:p], rtol=1e-10, atol=1e-12)
+            np.testing.assert_allclose(ev, ev_o, rtol=1e-10, atol=1e-12)
+            assert st["status"] == 0
+            Vh = host(V)
+            assert np.abs(Vh @ Vh.T - np.eye(p)).max() < 1e-10
+    S.close()
+
+
+@pytest.mark.parametrize("kw", [{"kmax": 16}, {"jd": 1, "kmax": 16, "jd_mmin": 8, "jd_mmax": 16}])
+def test_maximum_sizes(oracle_mod, kw):
+    """p = 32 eigenpairs (BNX_MAX_P; the widest kernel instantiations and the longest dot lists), a 16-pair
+    BFGS window (BNX_MAX_KMAX) and a 16-vector JD space, fp64 and mixed, against the oracle run with the
+    same options."""
+    A = mats()["diffusion_12"]
+    p = 32
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, _, st_o, _ = oracle_mod.solve(A, p, x0=x0, **kw)
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case max sizes", kw, prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0, **kw)
+        ev = ev.numpy()
+        np.testing.assert_allclose(ev, ev_o, rtol=1e-10)
+        check_pairs(A, ev, host(V), 1e-8)
+        assert st["status"] == 0
+    S.close()
