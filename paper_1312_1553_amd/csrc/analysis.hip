@@ -2,6 +2,7 @@
 // the transposed factor pattern and the level schedules of both triangular
 // solves.  Index work only; the factorisation itself runs on the device.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -69,6 +70,101 @@ static void build_levels(int n, const std::vector<int> &lev, Levels &L) {
   for (int i = 0; i < n; i++) L.rows[fill[lev[i]]++] = i;
   L.max_rows = 0;
   for (int l = 0; l < nlev; l++) L.max_rows = std::max(L.max_rows, L.ptr[l + 1] - L.ptr[l]);
+}
+
+void levels_from(int n, const std::vector<int> &lev, Levels &L) { build_levels(n, lev, L); }
+
+bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S) {
+  const int n = an.n;
+  const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
+  const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
+  const std::vector<int> &lev = lower ? an.levL.level : an.levLt.level;
+  const int nlev0 = lower ? an.levL.nlev : an.levLt.nlev;
+  auto deps = [&](int i, int &e0, int &e1) {
+    e0 = lower ? rp[i] : rp[i] + 1;
+    e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
+  };
+  auto diag = [&](int i) { return lower ? rp[i + 1] - 1 : rp[i]; };
+  S = SolveSys{};
+  S.n = n;
+  S.rp.assign(n + 1, 0);
+  S.mp.assign(n + 1, 0);
+  std::vector<int> slot(n, -1), cols;
+  std::vector<int> dir;                            // direct position of each new column
+  std::vector<std::vector<std::array<int, 3>>> tr;  // substitution terms of each new column
+  auto push_row = [&](int i) {
+    // columns ascending; the diagonal last (forward) or first (backward)
+    std::vector<int> ord(cols.size());
+    for (size_t t = 0; t < cols.size(); t++) ord[t] = (int)t;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+    auto put = [&](int col, int d, const std::vector<std::array<int, 3>> *terms) {
+      S.ci.push_back(col);
+      S.direct.push_back(d);
+      S.tp.push_back((int)S.ta.size());
+      if (terms)
+        for (const auto &x : *terms) {
+          S.ta.push_back(x[0]);
+          S.tb.push_back(x[1]);
+          S.tc.push_back(x[2]);
+        }
+    };
+    if (!lower) put(i, diag(i), nullptr);
+    for (int t : ord) put(cols[t], dir[t], &tr[t]);
+    if (lower) put(i, diag(i), nullptr);
+    S.rp[i + 1] = (int)S.ci.size();
+    for (int c : cols) slot[c] = -1;
+  };
+  bool fits = true;
+  for (int i = 0; i < n; i++) {
+    cols.clear();
+    dir.clear();
+    tr.clear();
+    auto col_of = [&](int k) {
+      if (slot[k] < 0) {
+        slot[k] = (int)cols.size();
+        cols.push_back(k);
+        dir.push_back(-1);
+        tr.emplace_back();
+      }
+      return slot[k];
+    };
+    int e0, e1;
+    deps(i, e0, e1);
+    const bool even = (lev[i] & 1) == 0;
+    for (int e = e0; e < e1; e++) {
+      const int j = ci[e];
+      if (even && (lev[j] & 1) == 1) {  // x_j = (b_j - sum_k v_jk x_k) / v_jj substituted into row i
+        S.mj.push_back(j);
+        S.ma.push_back(e);
+        S.mc.push_back(diag(j));
+        int f0, f1;
+        deps(j, f0, f1);
+        for (int f = f0; f < f1; f++) tr[col_of(ci[f])].push_back({e, f, diag(j)});
+      } else {
+        dir[col_of(j)] = e;
+      }
+    }
+    S.mp[i + 1] = (int)S.mj.size();
+    if ((int)cols.size() > maxdeps) fits = false;
+    push_row(i);
+  }
+  S.tp.push_back((int)S.ta.size());
+  S.nnz = (int)S.ci.size();
+  // levels of the new system
+  S.level.assign(n, 0);
+  auto level_of = [&](int i) {
+    int l = 0;
+    const int a = lower ? S.rp[i] : S.rp[i] + 1, b = lower ? S.rp[i + 1] - 1 : S.rp[i + 1];
+    for (int e = a; e < b; e++) l = std::max(l, S.level[S.ci[e]] + 1);
+    S.level[i] = l;
+  };
+  if (lower)
+    for (int i = 0; i < n; i++) level_of(i);
+  else
+    for (int i = n - 1; i >= 0; i--) level_of(i);
+  S.nlev = 0;
+  for (int i = 0; i < n; i++) S.nlev = std::max(S.nlev, S.level[i] + 1);
+  return fits && 4 * S.nlev <= 3 * nlev0;
 }
 
 void analyse(Analysis &an) {
@@ -284,21 +380,25 @@ struct Bisect {
 };
 }  // namespace
 
-int virtual_rows(int deps) { return deps <= kNR ? 0 : (deps - kNR + kNR - 2) / (kNR - 1); }
+int virtual_rows(int deps, int nr) { return deps <= nr ? 0 : (deps - nr + nr - 2) / (nr - 1); }
 
-bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split) {
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split,
+                    int nr, const Analysis *order) {
   const int n = an.n;
+  // the coordinates that order the blocks come from `order` (default: an itself): a graph whose
+  // edges, in both solve directions, compose every dependency of an's two systems
+  const Analysis &og = order ? *order : an;
   std::vector<int> vl, vu;
   if (split) {
     vl.resize(n);
     vu.resize(n);
     for (int i = 0; i < n; i++) {
-      vl[i] = virtual_rows(an.Lrp[i + 1] - an.Lrp[i] - 1);
-      vu[i] = virtual_rows(an.Ltrp[i + 1] - an.Ltrp[i] - 1);
+      vl[i] = virtual_rows(an.Lrp[i + 1] - an.Lrp[i] - 1, nr);
+      vu[i] = virtual_rows(an.Ltrp[i + 1] - an.Ltrp[i] - 1, nr);
     }
   }
   std::vector<int> co[3];
-  const int ncls = dag_coords(an, co);
+  const int ncls = dag_coords(og, co);
   rows.resize(n);
   for (int i = 0; i < n; i++) rows[i] = i;
   pstart.assign(1, 0);
@@ -308,7 +408,7 @@ bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::ve
     bi.vu = &vu;
   }
   for (int c = 0; c < ncls; c++) bi.coord.push_back(&co[c]);
-  bi.coord.push_back(&an.levL.level);
+  bi.coord.push_back(&og.levL.level);
   bi.stamp_in.assign(n, 0);
   bi.stamp_l.assign(n, 0);
   bi.stamp_u.assign(n, 0);
@@ -318,7 +418,7 @@ bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::ve
 }
 
 void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
-                    BlockSched &bs, bool split) {
+                    BlockSched &bs, bool split, int nr) {
   const int n = an.n;
   const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
   const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
@@ -330,9 +430,9 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
     e1 = lower ? rp[i + 1] - 1 : rp[i + 1];
   };
   // Items: the rows (ids 0..n-1) and, for a split schedule, virtual rows (ids n..): a
-  // row with m > kNR dependencies keeps its kNR-1 last-arriving ones plus the partial
-  // sum of the rest, which a chain of virtual rows computes (the first sums kNR
-  // dependencies, each further one the previous partial and kNR-1 more).  A virtual
+  // row with m > nr dependencies keeps its nr-1 last-arriving ones plus the partial
+  // sum of the rest, which a chain of virtual rows computes (the first sums nr
+  // dependencies, each further one the previous partial and nr-1 more).  A virtual
   // row has right-hand side 0 and diagonal 1, so its value is -sum L_ij x_j, and its
   // consumer reads it with weight -1 (valmap -2).  Edges list (source item, factor
   // position or -2); each row's dependencies are in the order their values appear
@@ -352,14 +452,14 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
       return glev[ci[a]] != glev[ci[c]] ? glev[ci[a]] < glev[ci[c]] : a < c;
     });
     const int m = e1 - e0;
-    const int nv = split ? virtual_rows(m) : 0;
+    const int nv = split ? virtual_rows(m, nr) : 0;
     int own0 = 0;  // first of the row's own entries in `order`
     if (nv > 0) {
-      const int c = m - (kNR - 1);  // entries summed by the chain
+      const int c = m - (nr - 1);  // entries summed by the chain
       int at = 0, prev = -1;
       for (int v = 0; v < nv; v++) {
         const int id = n + (int)vown.size();
-        const int take = std::min(c - at, v == 0 ? kNR : kNR - 1);
+        const int take = std::min(c - at, v == 0 ? nr : nr - 1);
         if (prev >= 0) {
           vsrc.push_back(prev);
           vval.push_back(-2);
@@ -420,6 +520,7 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
   }
   auto owner = [&](int it) { return it < n ? it : vown[it - n]; };
   bs.n = n;
+  bs.nr = nr;
   bs.nblocks = nb;
   bs.bptr.assign(nb + 1, 0);
   bs.brows.assign(nb, 0);
@@ -478,7 +579,7 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
       if (!ord.empty()) bs.max_local_levels = std::max(bs.max_local_levels, lx[ord.back()] - lx[ord.front()] + 1);
     }
   }
-  // ELL slices of 64 ranks for the dependencies beyond kNR
+  // ELL slices of 64 ranks for the dependencies beyond nr
   bs.nslices = npad / 64;
   bs.slice_ptr.assign(bs.nslices + 1, 0);
   bs.slice_nnz.assign(bs.nslices, 0);
@@ -489,17 +590,17 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
     int cnt;
     edges(item[k], src, val, cnt);
     bs.cnt[k] = cnt;
-    bs.slice_nnz[k / 64] = std::max(bs.slice_nnz[k / 64], cnt - kNR);
+    bs.slice_nnz[k / 64] = std::max(bs.slice_nnz[k / 64], cnt - nr);
   }
   for (int sl = 0; sl < bs.nslices; sl++) bs.slice_ptr[sl + 1] = bs.slice_ptr[sl] + 64 * bs.slice_nnz[sl];
-  // bit 30 of cnt flags the ranks of slices that hold rows longer than kNR
+  // bit 30 of cnt flags the ranks of slices that hold rows longer than nr
   for (int k = 0; k < npad; k++)
     if (bs.slice_nnz[k / 64] > 0) bs.cnt[k] |= kLongSlice;
   bs.ell = bs.slice_ptr[bs.nslices];
   bs.ref.assign(bs.ell, INT32_MIN);
   bs.valmap.assign(bs.ell, -1);
-  bs.ref4.assign((size_t)kNR * npad, INT32_MIN);
-  bs.valmap4.assign((size_t)kNR * npad, -1);
+  bs.ref4.assign((size_t)nr * npad, INT32_MIN);
+  bs.valmap4.assign((size_t)nr * npad, -1);
   // imports in order of first use, LDS slots
   bs.iptr.assign(nb + 1, 0);
   bs.irow.clear();
@@ -525,11 +626,11 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
           }
           slot = bs.brows[b] + imp_slot[j];
         }
-        if (e < kNR) {
+        if (e < nr) {
           bs.ref4[(size_t)e * npad + k] = -slot - 1;
           bs.valmap4[(size_t)e * npad + k] = val[e];
         } else {
-          const int at = bs.slice_ptr[sl] + 64 * (e - kNR) + lane;
+          const int at = bs.slice_ptr[sl] + 64 * (e - nr) + lane;
           bs.ref[at] = -slot - 1;
           bs.valmap[at] = val[e];
         }
@@ -539,7 +640,7 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
     // unused register-cached entries read the block's zero slot (value 0, weight 0)
     const int zero = -(bs.brows[b] + nimp) - 1;
     for (int k = bs.bptr[b]; k < bs.bptr[b + 1]; k++)
-      for (int q = 0; q < kNR; q++)
+      for (int q = 0; q < nr; q++)
         if (bs.ref4[(size_t)q * npad + k] == INT32_MIN) bs.ref4[(size_t)q * npad + k] = zero;
     bs.max_lds = std::max(bs.max_lds, bs.brows[b] + nimp + 1);
   }

@@ -87,7 +87,8 @@ struct Levels {
 // so a row always reads kNR values.  Further dependencies of long rows are
 // stored as 64-rank ELL slices: entry e >= kNR of lane l of slice s is at
 // slice_ptr[s] + 64 (e - kNR) + l (ELL padding: ref INT_MIN, valmap -1).
-constexpr int kNR = 4;
+constexpr int kNR = 4;   // dependency slots per row in registers (block solve)
+constexpr int kNRC = 6;  // the same for level-compressed systems
 constexpr int kLongSlice = 1 << 30;  // flag in cnt: the rank's slice has rows longer than kNR
 // LDS values per block (rows + imports + the zero slot): 159 KiB of the 160 KiB of a CU.
 constexpr int kLdsCap64 = 20352;
@@ -95,9 +96,11 @@ constexpr int kLdsCap32 = 40704;
 // default LDS values per block of the partition (measured on the 7-point 100^3 grid)
 constexpr int kBlkTarget64 = 7168;
 constexpr int kBlkTarget32 = 12288;
+constexpr int kBlkTarget32C = 8192;  // FP32, level-compressed systems: 256 blocks on the 100^3 grid
 
 struct BlockSched {
   int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;
+  int nr = kNR;                // dependency slots per rank (kNR or kNRC)
   int max_local_levels = 0, max_lds = 0;
   std::vector<int> bptr;       // nblocks+1: first (padded) rank of each block
   std::vector<int> brows;      // nblocks: LDS rows of each block (its rows, then their virtual rows)
@@ -130,6 +133,28 @@ struct Analysis {
   Levels levL, levLt;
 };
 
+// One direction's triangular system as the solves see it: rows of L for the forward
+// solve (dependencies, then the diagonal), rows of L^T for the backward one (the
+// diagonal, then the dependencies).  Its values come from that direction's factor
+// values v (L, or L^T, in CSR):
+//   entry e = (direct[e] >= 0 ? v[direct[e]] : 0) - sum_t v[ta[t]] v[tb[t]] / v[tc[t]],  t in [tp[e], tp[e+1]),
+// and the right-hand side is transformed first: b'_i = b_i - sum_t (v[ma[t]] / v[mc[t]]) b_{mj[t]},
+// t in [mp[i], mp[i+1]).  Level-pair substitution fills these (compress_system).
+struct SolveSys {
+  int n = 0, nnz = 0, nlev = 0;
+  std::vector<int> rp, ci, direct, tp, ta, tb, tc;
+  std::vector<int> mp, mj, ma, mc;
+  std::vector<int> level;
+};
+// Level-pair substitution: every row on an even level has each dependency on an odd
+// level replaced by that row's own equation, so it depends on rows further down and
+// the chain of dependent levels roughly halves (the solution is unchanged up to
+// rounding).  Returns false, leaving S unusable, when the levels do not drop below
+// 3/4 or a row would have more than maxdeps dependencies.
+bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S);
+// Level sets from per-row levels.
+void levels_from(int n, const std::vector<int> &lev, Levels &L);
+
 // Validate CSR; returns empty string if fine, else the problem.
 std::string validate_csr(int n, int nnz, const int *rp, const int *ci);
 // Build L / L^T patterns and level schedules.
@@ -142,14 +167,18 @@ void analyse(Analysis &an);
 // split: rows with more than kNR dependencies in either direction are solved
 // through chains of virtual partial-sum rows (block_schedule), which take LDS
 // slots of their own.
-bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split);
-// Virtual partial-sum rows a row with `deps` dependencies takes in a split schedule.
-int virtual_rows(int deps);
+// order: when the two solve systems of an are not transposes of each other (level-pair
+// substitution), the analysis of the factor they were derived from, whose coordinates are
+// monotone along the dependencies of both.
+bool partition_rows(const Analysis &an, int cap, std::vector<int> &rows, std::vector<int> &pstart, bool split,
+                    int nr, const Analysis *order = nullptr);
+// Virtual partial-sum rows a row with `deps` dependencies takes in a split schedule with nr slots.
+int virtual_rows(int deps, int nr);
 // Block schedule of the forward (lower = true: rows of L, diag last) or backward
 // (rows of L^T, diag first) solve over a partition from partition_rows (the
 // backward solve takes its blocks in reverse order).
 void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows, const std::vector<int> &pstart,
-                    BlockSched &bs, bool split);
+                    BlockSched &bs, bool split, int nr);
 
 // IC(lfil, tau_IC) factor of A + shift diag(A) (Sec. 2 initial preconditioner) in
 // CSR, rows with ascending columns and the diagonal last.  The dropping rule is
@@ -182,12 +211,21 @@ struct Mat {
 template <typename T>
 struct DevBlk {
   int n = 0, npad = 0, nblocks = 0;
+  int nr = kNR;           // dependency slots per rank (kNR, or kNRC for a level-compressed system)
   int nexp = 0, ell = 0;  // ell: entries in the ELL slices (0: no row has more than kNR dependencies)
   const int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *isrc = nullptr;
   const int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
   const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
   const int *cnt = nullptr, *ref4 = nullptr;
   const T *diag = nullptr, *val = nullptr, *val4 = nullptr;  // diag holds reciprocals
+  const int *rank = nullptr;  // rank of each row: the prep runs in row order and scatters (compressed systems)
+};
+
+// b'_i = b_i - sum_t mv[t] b_{mj[t]}, t in [mp[i], mp[i+1])
+template <typename T>
+struct RhsT {
+  const int *mp = nullptr, *mj = nullptr;
+  const T *mv = nullptr;
 };
 
 template <typename T>
@@ -203,6 +241,7 @@ struct Tri {
   int nlev = 0;
   int max_rows = 0;          // largest level
   bool lower = true;         // true: diag last (L); false: diag first (L^T)
+  RhsT<T> M;                 // right-hand-side transform of a level-compressed system (none: mp null)
 };
 
 // Optional HIP-event timing of the SpMV and triangular-solve launches.

@@ -239,18 +239,30 @@ __device__ __forceinline__ T rhs_value(int i, const T *b, int kfuse, const VList
   return s;
 }
 
+// right-hand side of row i of the system being solved: rhs_value, then the transform of a
+// level-compressed system (its substituted rows' right-hand sides, weighted)
+template <typename T>
+__device__ __forceinline__ T rhs_sys(int i, const T *b, int kfuse, const VList<T> &R, const double *coef,
+                                     const RhsT<T> &M) {
+  T s = rhs_value(i, b, kfuse, R, coef);
+  if (M.mp)
+    for (int t = M.mp[i]; t < M.mp[i + 1]; t++) s -= M.mv[t] * rhs_value(M.mj[t], b, kfuse, R, coef);
+  return s;
+}
+
 // One dependency level, one thread per row.  lower: x_i = (b_i - sum_{e<diag} L_e x_c)/L_diag (diag last);
 // upper (rows of L^T): x_i = (b_i - sum_{e>diag} Lt_e x_c)/Lt_diag (diag first).
 template <typename T, bool LOWER>
 __global__ __launch_bounds__(kBlock) void k_trsv_level(int r0, int r1, const int *__restrict__ rows,
                                                        const int *__restrict__ rp, const int *__restrict__ ci,
                                                        const T *__restrict__ v, const T *__restrict__ b, T *x,
-                                                       int kfuse, VList<T> R, const double *coef, const int *gate) {
+                                                       int kfuse, VList<T> R, const double *coef, RhsT<T> M,
+                                                       const int *gate) {
   if (gate && *gate) return;
   int pos = r0 + blockIdx.x * kBlock + threadIdx.x;
   if (pos >= r1) return;
   const int i = rows[pos];
-  T s = rhs_value(i, b, kfuse, R, coef);
+  T s = rhs_sys(i, b, kfuse, R, coef, M);
   const int e0 = rp[i], e1 = rp[i + 1];
   T d;
   if (LOWER) {
@@ -334,7 +346,8 @@ template <typename T, bool LOWER>
 __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict__ rows, const int *__restrict__ rp,
                                                     const int *__restrict__ ci, const T *__restrict__ v,
                                                     const T *__restrict__ b, T *x, int kfuse, VList<T> R,
-                                                    const double *coef, int *counter, int *err, const int *gate) {
+                                                    const double *coef, RhsT<T> M, int *counter, int *err,
+                                                    const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
   U *xu = reinterpret_cast<U *>(x);
@@ -348,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
     const int pos = (chunk << 6) + lane;
     if (pos < n) {
       const int i = rows[pos];
-      T s = rhs_value(i, b, kfuse, R, coef);
+      T s = rhs_sys(i, b, kfuse, R, coef, M);
       const int e0 = rp[i], e1 = rp[i + 1];
       int e, eend;
       T d;
@@ -393,20 +406,37 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int nexp, int npad, const int *__restrict__ perm,
                                                       const T *__restrict__ b, int kfuse, VList<T> R,
-                                                      const double *coef, T *bp, T *xe, int *counter,
+                                                      const double *coef, RhsT<T> M, T *bp, T *xe, int *counter,
                                                       const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
   if (part & 1)
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < npad; k += gridDim.x * kBlock) {
       const int i = perm[k];
-      bp[k] = i >= 0 ? rhs_value(i, b, kfuse, R, coef) : T(0);
+      bp[k] = i >= 0 ? rhs_sys(i, b, kfuse, R, coef, M) : T(0);
     }
   if (part & 2) {
     U *xu = reinterpret_cast<U *>(xe);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < nexp; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
   }
+}
+
+// The same prep in row order for a level-compressed system: its right-hand-side transform reads
+// neighbouring rows, which are close in row order and scattered in rank order; the result is
+// scattered to rank order instead (every rank of such a schedule is a row).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_trsv_prep_rows(int n, int nexp, const int *__restrict__ rank,
+                                                           const T *__restrict__ b, int kfuse, VList<T> R,
+                                                           const double *coef, RhsT<T> M, T *bp, T *xe,
+                                                           int *counter, const int *gate) {
+  if (gate && *gate) return;
+  using U = typename Sentinel<T>::U;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    bp[rank[i]] = rhs_sys(i, b, kfuse, R, coef, M);
+  U *xu = reinterpret_cast<U *>(xe);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nexp; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
 template <typename T, int NR>
@@ -449,12 +479,11 @@ __device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k
 // Every dependency of a row has a lower rank or is an import, so the lowest
 // unfinished row can always proceed.  Waits are bounded: on overflow the value
 // becomes NaN and *err is set.
-template <typename T, int CAP, bool LONG>
+template <typename T, int CAP, bool LONG, int NR>
 __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xe, int *counter,
                                                     int *err, const int *gate) {
   if (gate && *gate) return;
   using U = typename Sentinel<T>::U;
-  constexpr int NR = kNR;  // dependencies cached in registers per row
   constexpr int WC = BNX_TRSV_WC, WI = BNX_TRSV_WI;
   constexpr int WP = 16 - WC - WI;
   static_assert(WP >= 1 && WI >= 1, "wave roles");
@@ -763,11 +792,15 @@ void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, 
 
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  if (F.blk.ell > 0)
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, true>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+  // level-compressed systems (kNRC slots) have no row longer than kNRC: no general path
+  if (F.blk.nr == kNRC)
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, kNRC>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
+  else if (F.blk.ell > 0)
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, true, kNR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
                        reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
   else
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, kNR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
                        reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
 }
 
@@ -779,8 +812,13 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
     hipEvent_t ev0 = nullptr;
     T *bp = reinterpret_cast<T *>(F.blk_scratch);
     const int nb = grid_for((size_t)F.blk.npad, kNBMax);
-    hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, 3, F.blk.nexp, F.blk.npad, F.blk.perm, b,
-                       kfuse, R, coef, bp, reinterpret_cast<T *>(F.blk_exp), L.counter, gate);
+    if (F.blk.rank)
+      hipLaunchKernelGGL((k_trsv_prep_rows<T>), dim3(grid_for((size_t)F.n, kNBMax)), dim3(kBlock), 0, L.st, F.n,
+                         F.blk.nexp, F.blk.rank, b, kfuse, R, coef, F.M, bp, reinterpret_cast<T *>(F.blk_exp),
+                         L.counter, gate);
+    else
+      hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, 3, F.blk.nexp, F.blk.npad, F.blk.perm,
+                         b, kfuse, R, coef, F.M, bp, reinterpret_cast<T *>(F.blk_exp), L.counter, gate);
     if (prof0) L.prof->begin(L.st, &ev0);
     if constexpr (sizeof(T) == 8) launch_blk<T, kLdsCap64>(L, F, bp, x, gate);
     else launch_blk<T, kLdsCap32>(L, F, bp, x, gate);
@@ -797,10 +835,10 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
       int nb = (r1 - r0 + kBlock - 1) / kBlock;
       if (F.lower)
         hipLaunchKernelGGL((k_trsv_level<T, true>), dim3(nb), dim3(kBlock), 0, L.st, r0, r1, F.lev_rows, F.rp, F.ci,
-                           F.v, b, x, kfuse, R, coef, gate);
+                           F.v, b, x, kfuse, R, coef, F.M, gate);
       else
         hipLaunchKernelGGL((k_trsv_level<T, false>), dim3(nb), dim3(kBlock), 0, L.st, r0, r1, F.lev_rows, F.rp,
-                           F.ci, F.v, b, x, kfuse, R, coef, gate);
+                           F.ci, F.v, b, x, kfuse, R, coef, F.M, gate);
     }
     if (prof) L.prof->end(L.st, pid, ev);
     return;
@@ -819,10 +857,10 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
   if (prof) L.prof->begin(L.st, &ev);
   if (F.lower)
     hipLaunchKernelGGL((k_trsv_sf<T, true>), dim3(nb), dim3(kBlock), 0, L.st, F.n, F.lev_rows, F.rp, F.ci, F.v, b, x,
-                       kfuse, R, coef, L.counter, err, gate);
+                       kfuse, R, coef, F.M, L.counter, err, gate);
   else
     hipLaunchKernelGGL((k_trsv_sf<T, false>), dim3(nb), dim3(kBlock), 0, L.st, F.n, F.lev_rows, F.rp, F.ci, F.v, b,
-                       x, kfuse, R, coef, L.counter, err, gate);
+                       x, kfuse, R, coef, F.M, L.counter, err, gate);
   if (prof) L.prof->end(L.st, pid, ev);
 }
 

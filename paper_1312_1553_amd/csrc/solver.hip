@@ -837,6 +837,19 @@ __global__ void k_gather_blk(int m, const int *map, const double *src, T *dst) {
   }
 }
 
+// values of a level-compressed system from the factor values v of its direction (SolveSys)
+__global__ void k_sys_values(int nnz, const int *direct, const int *tp, const int *ta, const int *tb, const int *tc,
+                             const double *v, double *out) {
+  GRIDLOOP(e, nnz) {
+    double x = direct[e] >= 0 ? v[direct[e]] : 0.0;
+    for (int t = tp[e]; t < tp[e + 1]; t++) x -= v[ta[t]] * v[tb[t]] / v[tc[t]];
+    out[e] = x;
+  }
+}
+__global__ void k_sys_m(int nm, const int *ma, const int *mc, const double *v, double *out) {
+  GRIDLOOP(t, nm) out[t] = v[ma[t]] / v[mc[t]];
+}
+
 // reciprocal diagonal of a block schedule: dst[k] = 1 / src[map[k]] (rounded once, in double)
 template <typename T>
 __global__ void k_gather_rdiag(int m, const int *map, const double *src, T *dst) {
@@ -950,14 +963,28 @@ struct bnx_ctx {
   float *Lv32 = nullptr, *Ltv32 = nullptr;
   // block schedules of the LDS-staged solve: [0] forward (L), [1] backward (L^T); per precision
   struct BlkDev {
-    int n = 0, npad = 0, nblocks = 0, ell = 0, nexp = 0;
+    int n = 0, npad = 0, nblocks = 0, ell = 0, nexp = 0, nr = kNR;
     int *bptr = nullptr, *brows = nullptr, *iptr = nullptr, *isrc = nullptr;
     int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
     int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
     int *valmap = nullptr, *diagmap = nullptr, *cnt = nullptr, *ref4 = nullptr, *valmap4 = nullptr;
+    int *rank = nullptr;  // rank of each row, for the row-order prep of a level-compressed schedule
     double *diag64 = nullptr, *val64 = nullptr, *val4_64 = nullptr;
     float *diag32 = nullptr, *val32 = nullptr, *val4_32 = nullptr;
   } blk[2][2];  // [direction][0 = fp64 LDS capacity, 1 = fp32 LDS capacity]
+  // Level-compressed solve systems ([0] forward, [1] backward; compress_system), used by the
+  // FP32 solves when lps is set (in FP64 the compressed kernel gains nothing measurable); the
+  // other solves use the factor's own rows (Lrp/Lci/Lv and Ltrp/Ltci/Ltv).
+  bool lps = false;
+  Analysis anS;  // their patterns and levels: forward system in L*, backward system in Lt*
+  struct SysDev {
+    int nnz = 0, nm = 0;
+    int *rp = nullptr, *ci = nullptr, *lev = nullptr;
+    int *direct = nullptr, *tp = nullptr, *ta = nullptr, *tb = nullptr, *tc = nullptr;
+    int *mp = nullptr, *mj = nullptr, *ma = nullptr, *mc = nullptr;
+    double *v = nullptr, *mv = nullptr;
+    float *v32 = nullptr, *mv32 = nullptr;
+  } sys[2];
   double *blk_rhs = nullptr;  // right-hand side of a block solve in rank order (largest npad)
   double *blk_exp = nullptr;  // export buffer of a block solve (largest nexp)
   int *probe_flags = nullptr;  // latency probe flags (allocated on first use)
@@ -1067,6 +1094,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   {
     const BlkDev &b = blk[lower ? 0 : 1][0];
     F.blk.n = b.n;
+    F.blk.nr = b.nr;
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
     F.blk.nexp = b.nexp;
@@ -1097,7 +1125,8 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   F.ci = lower ? Lci : Ltci;
   F.v = lower ? Lv : Ltv;
   F.lev_rows = lower ? levL : levLt;
-  const Levels &lv = lower ? ta->levL : ta->levLt;
+  const Analysis &la = *ta;
+  const Levels &lv = lower ? la.levL : la.levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
@@ -1109,6 +1138,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
   {
     const BlkDev &b = blk[lower ? 0 : 1][1];
     F.blk.n = b.n;
+    F.blk.nr = b.nr;
     F.blk.npad = b.npad;
     F.blk.nblocks = b.nblocks;
     F.blk.nexp = b.nexp;
@@ -1130,16 +1160,29 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.cnt = b.cnt;
     F.blk.ref4 = b.ref4;
     F.blk.val4 = b.val4_32;
+    F.blk.rank = b.rank;
   }
   F.blk_scratch = blk_rhs;
   F.blk_exp = blk_exp;
   F.n = n;
   F.lower = lower;
-  F.rp = lower ? Lrp : Ltrp;
-  F.ci = lower ? Lci : Ltci;
-  F.v = lower ? Lv32 : Ltv32;
-  F.lev_rows = lower ? levL : levLt;
-  const Levels &lv = lower ? ta->levL : ta->levLt;
+  if (lps) {
+    const SysDev &S = sys[lower ? 0 : 1];
+    F.rp = S.rp;
+    F.ci = S.ci;
+    F.v = S.v32;
+    F.lev_rows = S.lev;
+    F.M.mp = S.mp;
+    F.M.mj = S.mj;
+    F.M.mv = S.mv32;
+  } else {
+    F.rp = lower ? Lrp : Ltrp;
+    F.ci = lower ? Lci : Ltci;
+    F.v = lower ? Lv32 : Ltv32;
+    F.lev_rows = lower ? levL : levLt;
+  }
+  const Analysis &la = lps ? anS : *ta;
+  const Levels &lv = lower ? la.levL : la.levLt;
   F.lev_ptr = lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
@@ -1767,6 +1810,9 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     double theta = h.otheta, rn = h.orn;
     std::deque<int> ring;  // chronological slots
     int k = 0, slow = 0, restarts = 0;
+    double best = rn;  // mixed precision: smallest outer residual so far
+    int since_best = 0;
+
     while (!alone && rn > o.tol * theta && k < o.itmax) {
       const int m = j + 1;
       VList<T> Q = QtT;
@@ -1891,11 +1937,22 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
       theta = h.otheta;
       rn = h.orn;
       k++;
-      if ((its == 0 || slow >= 2) && restarts < 5 && rn > o.tol * theta && k < o.itmax) {
+      // Mixed precision: the float inner solves bound how far the outer residual can fall.  When
+      // it is below 1e-7 theta (float territory) and has not improved on its best by 10 % for
+      // three steps (it oscillates at that floor rather than stalling), the pair is finished by
+      // the double DACG to tau.
+      if (rn < 0.9 * best) {
+        best = rn;
+        since_best = 0;
+      } else {
+        since_best++;
+      }
+      const bool floor = !fp64 && since_best >= 3 && rn < 1e-7 * theta;
+      if ((its == 0 || slow >= 2 || floor) && restarts < 5 && rn > o.tol * theta && k < o.itmax) {
         // the start was not close enough (Sec. 4.1): resume DACG from u with a tighter tolerance,
         // restart the BFGS history, then continue Newton
         const double td2 = now_s();
-        const double t2 = std::min(o.tol_dacg, std::max(o.tol, 0.1 * rn / theta));
+        const double t2 = floor ? o.tol : std::min(o.tol_dacg, std::max(o.tol, 0.1 * rn / theta));
         long long mvp2 = 0;
         if (fp64) {
           launch_cast<double, T>(C->st, n, u, w.x);
@@ -1922,6 +1979,8 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
         restarts++;
         S.dacg_restarts++;
         slow = 0;
+        best = rn;
+        since_best = 0;
         S.t_dacg += now_s() - td2;
       }
     }
@@ -1969,8 +2028,9 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
   bool allc = true;
   for (int jj = 0; jj < p; jj++) allc = allc && So.converged[jj];
   So.status = allc ? BNX_OK : BNX_NOT_CONVERGED;
-  So.levels_L = C->ta->levL.nlev;
-  So.levels_Lt = C->ta->levLt.nlev;
+  const Analysis &run_an = (C->lps && !fp64) ? C->anS : *C->ta;  // the systems this solve's substitutions ran
+  So.levels_L = run_an.levL.nlev;
+  So.levels_Lt = run_an.levLt.nlev;
   So.nnz_L = C->ta->nnzL;
   So.fill = (double)C->ta->nnzL / (double)C->an.nnzL;
   So.shift_used = C->shift_used;
@@ -2133,7 +2193,7 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     for (int pr = 0; pr < 2; pr++) {
       auto &b = C->blk[dir][pr];
       for (int *q : {b.bptr, b.brows, b.iptr, b.isrc, b.eptr, b.erank, b.orow, b.oslot, b.perm, b.slice_ptr,
-                     b.slice_nnz, b.ref, b.valmap, b.diagmap, b.cnt, b.ref4, b.valmap4})
+                     b.slice_nnz, b.ref, b.valmap, b.diagmap, b.cnt, b.ref4, b.valmap4, b.rank})
         C->release(q);
       for (double *q : {b.diag64, b.val64, b.val4_64}) C->release(q);
       for (float *q : {b.diag32, b.val32, b.val4_32}) C->release(q);
@@ -2142,6 +2202,13 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   for (int *q : {C->Lrp, C->Lci, C->mapL, C->Ltrp, C->Ltci, C->mapLt, C->levL, C->levLt}) C->release(q);
   for (double *q : {C->Lv, C->Ltv, C->blk_rhs, C->blk_exp}) C->release(q);
   for (float *q : {C->Lv32, C->Ltv32}) C->release(q);
+  for (auto &S : C->sys) {
+    for (int *q : {S.rp, S.ci, S.lev, S.direct, S.tp, S.ta, S.tb, S.tc, S.mp, S.mj, S.ma, S.mc}) C->release(q);
+    for (double *q : {S.v, S.mv}) C->release(q);
+    for (float *q : {S.v32, S.mv32}) C->release(q);
+    S = bnx_ctx::SysDev{};
+  }
+  C->lps = false;
   C->ta = nullptr;
   C->factored = false;
   C->solved = false;
@@ -2167,26 +2234,80 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   HIPCHK(hipMemcpyAsync(C->mapLt, a.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levL, a.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levLt, a.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
-  // Long rows (more than kNR dependencies) through chains of virtual partial-sum rows, so
-  // every row of the block solve takes its branch-free four-slot path
+  // Level-pair substitution (compress_system) when it shortens both dependency chains below
+  // 3/4 and keeps every row within kNRC dependencies: the solves then run the two compressed
+  // systems, whose values finish_factor derives from the factor's.
+  bool lps = true;
+  if (const char *e = getenv("BNX_LPS")) lps = atoi(e) != 0;  // tuning override
+  {
+    SolveSys Sf, Sb;
+    C->lps = lps && compress_system(a, true, kNRC, Sf) && compress_system(a, false, kNRC, Sb);
+    if (C->lps) {
+      Analysis &S = C->anS;
+      S = Analysis{};
+      S.n = n;
+      S.Lrp = Sf.rp;
+      S.Lci = Sf.ci;
+      S.Ltrp = Sb.rp;
+      S.Ltci = Sb.ci;
+      S.nnzL = Sf.nnz;
+      levels_from(n, Sf.level, S.levL);
+      levels_from(n, Sb.level, S.levLt);
+      auto up = [&](const std::vector<int> &v) {
+        int *d = C->alloc<int>(std::max<size_t>(v.size(), 1));
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, C->st));
+        return d;
+      };
+      for (int d = 0; d < 2; d++) {
+        const SolveSys &Q = d == 0 ? Sf : Sb;
+        auto &D = C->sys[d];
+        D.nnz = Q.nnz;
+        D.nm = (int)Q.mj.size();
+        D.rp = up(Q.rp);
+        D.ci = up(Q.ci);
+        D.lev = up(d == 0 ? S.levL.rows : S.levLt.rows);
+        D.direct = up(Q.direct);
+        D.tp = up(Q.tp);
+        D.ta = up(Q.ta);
+        D.tb = up(Q.tb);
+        D.tc = up(Q.tc);
+        D.mp = up(Q.mp);
+        D.mj = up(Q.mj);
+        D.ma = up(Q.ma);
+        D.mc = up(Q.mc);
+        D.v = C->alloc<double>(Q.nnz);
+        D.v32 = C->alloc<float>(Q.nnz);
+        D.mv = C->alloc<double>(std::max(D.nm, 1));
+        D.mv32 = C->alloc<float>(std::max(D.nm, 1));
+      }
+      C->sync();  // host vectors go out of scope
+    }
+  }
+  // Long rows (more than nr dependencies) through chains of virtual partial-sum rows, so
+  // every row of the block solve takes its branch-free path
   bool split = true;
   if (const char *e = getenv("BNX_SPLIT_LONG")) split = atoi(e) != 0;  // tuning override
   for (int pr = 0; pr < 2; pr++) {
     std::vector<int> prow, pstart;
     // Block size target: larger blocks cross fewer block boundaries, smaller ones
     // keep more waves per level busy; measured best near 7k (FP64) and 12k (FP32)
-    // rows on the 7-point 100^3 grid.
-    int cap = pr == 0 ? kBlkTarget64 : kBlkTarget32;
+    // rows on the 7-point 100^3 grid, and 8k in FP32 for the level-compressed systems
+    // (their levels hold twice the rows: 256 blocks beat 128).
+    const bool cmp = C->lps && pr == 1;  // FP32 schedules of the compressed systems
+    const Analysis &sa = cmp ? C->anS : a;
+    const int nr = cmp ? kNRC : kNR;
+    int cap = pr == 0 ? kBlkTarget64 : (cmp ? kBlkTarget32C : kBlkTarget32);
     if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
       cap = atoi(e);
     cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
-    if (!partition_rows(a, cap, prow, pstart, split)) continue;  // no block schedule
+    if (!partition_rows(sa, cap, prow, pstart, split, nr, cmp ? &a : nullptr)) continue;  // no block schedule
     for (int dir = 0; dir < 2; dir++) {
       BlockSched bs;
-      block_schedule(a, dir == 0, prow, pstart, bs, split);
+      block_schedule(sa, dir == 0, prow, pstart, bs, split, nr);
       if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
       auto &b = C->blk[dir][pr];
       b.n = bs.n;
+      b.nr = bs.nr;
       b.npad = bs.npad;
       b.nblocks = bs.nblocks;
       b.ell = bs.ell;
@@ -2214,15 +2335,25 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
       b.cnt = up(bs.cnt);
       b.ref4 = up(bs.ref4);
       b.valmap4 = up(bs.valmap4);
+      // row-order prep: every rank of a block is a row (no virtual rows), so scattering the
+      // rows covers every rank the solve reads
+      bool rows_only = cmp;
+      for (int q = 0; q < bs.nblocks && rows_only; q++) rows_only = bs.nreal[q] == bs.brows[q];
+      if (rows_only) {
+        std::vector<int> rk(bs.n, 0);
+        for (int k = 0; k < bs.npad; k++)
+          if (bs.perm[k] >= 0) rk[bs.perm[k]] = k;
+        b.rank = up(rk);
+      }
       const size_t np = (size_t)bs.npad;
       if (pr == 0) {
         b.diag64 = C->alloc<double>(np);
         b.val64 = C->alloc<double>(std::max(bs.ell, 1));
-        b.val4_64 = C->alloc<double>((size_t)kNR * np);
+        b.val4_64 = C->alloc<double>((size_t)bs.nr * np);
       } else {
         b.diag32 = C->alloc<float>(np);
         b.val32 = C->alloc<float>(std::max(bs.ell, 1));
-        b.val4_32 = C->alloc<float>((size_t)kNR * np);
+        b.val4_32 = C->alloc<float>((size_t)bs.nr * np);
       }
       C->sync();  // host vectors go out of scope
     }
@@ -2304,9 +2435,21 @@ void finish_factor(bnx_ctx *C) {
   hipLaunchKernelGGL(k_gather_d, dim3(gridn(nnzL)), dim3(kBlock), 0, C->st, nnzL, C->mapLt, C->Lv, C->Ltv);
   launch_cast<double, float>(C->st, nnzL, C->Lv, C->Lv32);
   launch_cast<double, float>(C->st, nnzL, C->Ltv, C->Ltv32);
+  if (C->lps)
+    for (int d = 0; d < 2; d++) {
+      auto &S = C->sys[d];
+      const double *v = d == 0 ? C->Lv : C->Ltv;
+      hipLaunchKernelGGL(k_sys_values, dim3(gridn(S.nnz)), dim3(kBlock), 0, C->st, S.nnz, S.direct, S.tp, S.ta, S.tb,
+                         S.tc, v, S.v);
+      launch_cast<double, float>(C->st, S.nnz, S.v, S.v32);
+      if (S.nm > 0) {
+        hipLaunchKernelGGL(k_sys_m, dim3(gridn(S.nm)), dim3(kBlock), 0, C->st, S.nm, S.ma, S.mc, v, S.mv);
+        launch_cast<double, float>(C->st, S.nm, S.mv, S.mv32);
+      }
+    }
   for (int dir = 0; dir < 2; dir++) {
-    const double *src = dir == 0 ? C->Lv : C->Ltv;
     for (int pr = 0; pr < 2; pr++) {
+      const double *src = (C->lps && pr == 1) ? C->sys[dir].v : (dir == 0 ? C->Lv : C->Ltv);
       auto &b = C->blk[dir][pr];
       if (b.nblocks == 0) continue;
       const int np = b.npad;
@@ -2315,14 +2458,14 @@ void finish_factor(bnx_ctx *C) {
                            b.diag64);
         hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val64);
-        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(kNR * np)), dim3(kBlock), 0, C->st, kNR * np,
+        hipLaunchKernelGGL((k_gather_blk<double>), dim3(gridn(b.nr * np)), dim3(kBlock), 0, C->st, b.nr * np,
                            b.valmap4, src, b.val4_64);
       } else {
         hipLaunchKernelGGL((k_gather_rdiag<float>), dim3(gridn(np)), dim3(kBlock), 0, C->st, np, b.diagmap, src,
                            b.diag32);
         hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(b.ell)), dim3(kBlock), 0, C->st, b.ell, b.valmap, src,
                            b.val32);
-        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(kNR * np)), dim3(kBlock), 0, C->st, kNR * np,
+        hipLaunchKernelGGL((k_gather_blk<float>), dim3(gridn(b.nr * np)), dim3(kBlock), 0, C->st, b.nr * np,
                            b.valmap4, src, b.val4_32);
       }
     }

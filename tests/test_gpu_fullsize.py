@@ -103,6 +103,8 @@ def test_fullsize_c1_solve_matches_oracle():
         ev, V, st = S.solve(p, precision=prec, x0=x0)
         ev = ev.numpy()
         assert st["status"] == 0 and all(st["converged"][:p])
+        # FP32 substitutions run the level-compressed systems (298 -> 150 levels), FP64 the factor's own
+        assert (st["levels_L"], st["levels_Lt"]) == ((298, 298) if prec == FP64 else (150, 150))
         # both sides stop at ||r|| <= 1e-8 theta; the eigenvalue error is then O(||r||^2 / gap), far below 1e-10
         rel = np.abs(ev - ref) / ref
         say("  max rel eigenvalue difference vs oracle", rel.max())
