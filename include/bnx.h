@@ -117,7 +117,8 @@ typedef struct {
     int bfgs_skipped;           /* pairs not stored because s^T r >= -1e-12 ||s|| ||r|| */
     int pcg_breakdowns;         /* PCG stops with p^T J p <= 0 */
     int status;                 /* bnx_status of the solve */
-    int levels_L, levels_Lt;    /* dependency levels of the IC(0) triangular solves */
+    int levels_L, levels_Lt;    /* dependency levels of the triangular systems this solve substituted
+                                   (its FP32 solves run level-compressed systems when they apply) */
     double shift_used;          /* IC(0) diagonal shift actually used */
     double t_factor, t_dacg, t_newton;  /* seconds */
     int dacg_restarts;          /* returns from a stalled Newton phase to DACG (see bnx_solve) */
@@ -161,7 +162,7 @@ bnx_status bnx_factor(bnx_ctx *ctx, const bnx_factor_opts *opts);
 
 /* Size of the installed factor (Sec. 5 reports the fill ratio sigma of the
  * initial preconditioner): nnz(L) with the diagonal, sigma = nnz(L)/nnz(tril A),
- * the dependency levels of the L and L^T solves and the diagonal shift used.
+ * the dependency levels of the factor's L and L^T solves and the diagonal shift used.
  * Any output pointer may be NULL.  Errors: BNX_E_ARG, BNX_E_STATE before bnx_factor. */
 bnx_status bnx_factor_info(const bnx_ctx *ctx, long long *nnz_L, double *fill, int *levels_L, int *levels_Lt,
                            double *shift_used);

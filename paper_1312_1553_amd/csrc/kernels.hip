@@ -223,6 +223,8 @@ int launch_multidot(const Launch &L, int n, int D, const VList<T> &X, const VLis
     hipLaunchKernelGGL((k_multidot<T, Acc, 4>), dim3(nb), dim3(kBlock), 0, L.st, n, D, X, Y, part, gate);
   else if (D <= 16)
     hipLaunchKernelGGL((k_multidot<T, Acc, 16>), dim3(nb), dim3(kBlock), 0, L.st, n, D, X, Y, part, gate);
+  else if (D <= 24)  // the DACG dots of up to 11 deflated vectors (2 nq + 1) without the registers of 48
+    hipLaunchKernelGGL((k_multidot<T, Acc, 24>), dim3(nb), dim3(kBlock), 0, L.st, n, D, X, Y, part, gate);
   else if (D <= 48)
     hipLaunchKernelGGL((k_multidot<T, Acc, 48>), dim3(nb), dim3(kBlock), 0, L.st, n, D, X, Y, part, gate);
   else

@@ -2335,8 +2335,9 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
       b.cnt = up(bs.cnt);
       b.ref4 = up(bs.ref4);
       b.valmap4 = up(bs.valmap4);
-      // row-order prep: every rank of a block is a row (no virtual rows), so scattering the
-      // rows covers every rank the solve reads
+      // row-order prep for the compressed systems (their right-hand-side transform reads
+      // neighbouring rows): every rank of a block must be a row (no virtual rows), so that
+      // scattering the rows covers every rank the solve reads
       bool rows_only = cmp;
       for (int q = 0; q < bs.nblocks && rows_only; q++) rows_only = bs.nreal[q] == bs.brows[q];
       if (rows_only) {
