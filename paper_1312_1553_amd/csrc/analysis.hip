@@ -74,6 +74,14 @@ static void build_levels(int n, const std::vector<int> &lev, Levels &L) {
 
 void levels_from(int n, const std::vector<int> &lev, Levels &L) { build_levels(n, lev, L); }
 
+int slots_for(const Analysis &sys, bool compressed) {
+  int m = 0;
+  for (int i = 0; i < sys.n; i++)
+    m = std::max(m, std::max(sys.Lrp[i + 1] - sys.Lrp[i], sys.Ltrp[i + 1] - sys.Ltrp[i]) - 1);
+  if (m <= 3) return 3;
+  return compressed ? kNRC : kNR;
+}
+
 bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S) {
   const int n = an.n;
   const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;

@@ -154,6 +154,10 @@ struct SolveSys {
 bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S);
 // Level sets from per-row levels.
 void levels_from(int n, const std::vector<int> &lev, Levels &L);
+// Register slots of the block solve for the two systems of an analysis: 3 when no row of
+// either has more than three dependencies (each slot costs a load per polling round),
+// else kNR, or kNRC for level-compressed systems.
+int slots_for(const Analysis &sys, bool compressed);
 
 // Validate CSR; returns empty string if fine, else the problem.
 std::string validate_csr(int n, int nnz, const int *rp, const int *ci);

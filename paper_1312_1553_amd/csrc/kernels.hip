@@ -794,8 +794,12 @@ void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, 
 
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  // level-compressed systems (kNRC slots) have no row longer than kNRC: no general path
-  if (F.blk.nr == kNRC)
+  // three-slot schedules (no row longer than three) and level-compressed systems (kNRC slots,
+  // no row longer than kNRC) need no general path
+  if (F.blk.nr == 3)
+    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, 3>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
+                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
+  else if (F.blk.nr == kNRC)
     hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, kNRC>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
                        reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
   else if (F.blk.ell > 0)

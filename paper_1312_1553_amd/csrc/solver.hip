@@ -2295,7 +2295,7 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     // (their levels hold twice the rows: 256 blocks beat 128).
     const bool cmp = C->lps && pr == 1;  // FP32 schedules of the compressed systems
     const Analysis &sa = cmp ? C->anS : a;
-    const int nr = cmp ? kNRC : kNR;
+    const int nr = slots_for(sa, cmp);
     int cap = pr == 0 ? kBlkTarget64 : (cmp ? kBlkTarget32C : kBlkTarget32);
     if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
       cap = atoi(e);

@@ -246,8 +246,8 @@ static void run(Analysis &an, int cap, const char *name, bool split, bool lps) {
       }
     }
     sys = &cs;
-    nr = kNRC;
   }
+  nr = slots_for(*sys, lps);
   std::vector<int> rows, pstart;
   if (!partition_rows(*sys, cap, rows, pstart, split, nr, lps ? &an : nullptr)) {
     printf("%s: partition infeasible\n", name);
@@ -256,8 +256,8 @@ static void run(Analysis &an, int cap, const char *name, bool split, bool lps) {
   }
   for (int d = 0; d < 2; d++) {
     const double err = emulate(*sys, d == 0, rows, pstart, split, nr, cap, F[d], rhs[d], ref[d]);
-    printf("%s%s%s %s: blocks %zu, error %.2e\n", name, split ? " split" : "", lps ? " lps" : "",
-           d == 0 ? "forward" : "backward", pstart.size() - 1, err);
+    printf("%s%s%s %s: blocks %zu, slots %d, error %.2e\n", name, split ? " split" : "", lps ? " lps" : "",
+           d == 0 ? "forward" : "backward", pstart.size() - 1, nr, err);
     CHECK(err < 1e-10, "solution differs from substitution");
   }
 }
