@@ -105,7 +105,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=100, help="cells per side (100 = the headline n = 10^6 case)")
-    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--p", type=int, default=0, help="eigenpairs (default: the workload's, 10 for the headline)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4"], default="c1",
+                    help="c1: 3-D diffusion (the headline); c2: Q1 elasticity 50^3 elements, p = 20; c3: geometric "
+                         "graph Laplacian, 500k nodes, p = 10; c4: 64^3 diffusion, p = 5, solve + backward of "
+                         "sum(lambda) + sum_j w_j v_1[j]^2")
     ap.add_argument("--trsv-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-grid", type=int, default=100)
@@ -137,12 +141,22 @@ def main():
     from paper_1312_1553_amd import bnx
     from paper_1312_1553_amd import workloads as W
 
-    N, p = args.grid, args.p
+    N = args.grid
     t0 = time.time()
-    A = W.diffusion_3d(N, seed=1)
+    wgrad = None
+    if args.workload == "c2":
+        p, A, wname = args.p or 20, W.elasticity_q1(50, seed=2), "elasticity_q1_50^3_lognormal_seed2"
+    elif args.workload == "c3":
+        p, A, wname = args.p or 10, W.rgg_laplacian(500_000, seed=3), "rgg_laplacian_500k_seed3_rcm"
+    elif args.workload == "c4":
+        pat, logk, wgrad = W.diffusion_grad_case(64, seed=4)
+        p, A, wname = args.p or 5, pat.csr(logk), "diffusion3d_64^3_seed4_solve_and_backward"
+    else:
+        p, A, wname = args.p or 10, W.diffusion_3d(N, seed=1), f"diffusion3d_{N}^3_lognormal_seed1"
+    if args.workload != "c1":
+        args.no_cpu_baseline = True  # the oracle sample is defined on the headline workload
     x0 = W.initial_block(A.n, p, 0)
-    print(f"[bench] workload diffusion3d {N}^3 n={A.n} nnz={A.nnz} p={p} built in {time.time() - t0:.1f}s",
-          flush=True)
+    print(f"[bench] workload {wname} n={A.n} nnz={A.nnz} p={p} built in {time.time() - t0:.1f}s", flush=True)
     torch.cuda.set_device(0)
     S = bnx.Solver(A.rowptr, A.col, A.val)
     bnx.bnx_set_trsv_mode(S.h, args.trsv_mode)
@@ -184,6 +198,10 @@ def main():
             S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
                                  kmax=args.kmax)
+            if wgrad is not None:  # C4: the backward of the loss through the same solve
+                GV = torch.zeros_like(V)
+                GV[0] = 2 * torch.as_tensor(wgrad, device=V.device) * V[0]
+                S.backward(np.ones(p), GV)
             stats.append(st)
             print(f"[bench] {name} step {k}: status {st['status']} (elapsed {time.perf_counter() - t0:.2f}s)",
                   flush=True)
@@ -201,6 +219,8 @@ def main():
         print(f"[bench] {name}: {results[name]['eps']:.3f} eigenpairs/s, {results[name]['ms']:.1f} ms/step, "
               f"max relres {relres:.2e}, pcg its {sum(st['pcg_its'])}, dacg its {sum(st['dacg_its'])}, "
               f"outer its {sum(st['outer_its'])}", flush=True)
+        print(f"[bench]   per pair: dacg its {list(st['dacg_its'])}, pcg its {list(st['pcg_its'])}, "
+              f"dacg restarts {st.get('dacg_restarts')}", flush=True)
         for kname, (ms, cnt) in kt.items():
             if cnt:
                 print(f"[bench]   {kname}: {cnt} launches, avg {1000 * ms / cnt:.1f} us, total {ms:.1f} ms",
@@ -233,7 +253,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
-        Ac = A if args.cpu_sample_grid == N else W.diffusion_3d(args.cpu_sample_grid, seed=1)
+        Ac = A if args.cpu_sample_grid == N and args.workload == "c1" else W.diffusion_3d(args.cpu_sample_grid, seed=1)
         x0c = W.initial_block(Ac.n, 1, 0)
         t0 = time.perf_counter()
         ev_o, V_o, st_o, _ = oracle.solve(Ac, 1, x0=x0c)
@@ -258,7 +278,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 inner / f64 outer (mixed); fp64 path reported beside it",
         "data": "synthetic",
-        "config": {"workload": f"diffusion3d_{N}^3_lognormal_seed1", "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
+        "config": {"workload": wname, "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
                    "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
                    "method": ("Jacobi-Davidson" if args.jd else "DACG-Newton" if args.newton else "DACG alone"),
                    "kmax": args.kmax,
@@ -275,7 +295,7 @@ def main():
                                                        / np.array(fp64["evals"]))),
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": counter_traffic(kname, N),
+                     "traffic": counter_traffic(kname, N) if args.workload == "c1" else None,
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                      "levels": levels,
                      "limiter": ("latency: a chain of %d dependent levels" % levels) if kname.startswith("trsv")

@@ -13,6 +13,7 @@ constexpr int kMaxK = 16;      // BFGS window
 constexpr int kMaxQ = kMaxP + 1;
 constexpr int kMaxVec = 80;    // vectors in one kernel argument list
 constexpr int kJdMax = 16;     // largest Jacobi-Davidson search space
+constexpr int kDacgStall = 200;  // float DACG: iterations without a 10 % gain that end it near tau
 #ifndef BNX_NBMAX
 #define BNX_NBMAX 2048
 #endif
@@ -42,6 +43,8 @@ struct DevCtl {
   // DACG (Sec. 4.1)
   double dq, dxx, dxAx, dgamma, dgamma_prev, dalpha, dinv, dgn, dtol;
   int dits, ddone, ditmax;
+  double dbest;                     // smallest ||g||/||x|| so far
+  int dbest_it, dstall, dstalled;   // its iteration; stall window (0: off); set when the window ended it
   // outer step (always double)
   double oz[kMaxQ], onrm2, otheta, orn, oalpha, osn2, ornold;
   double oya, oyn2;  // s^T (r_k - r_{k+1}) and ||r_k - r_{k+1}||^2 for the full BFGS pair

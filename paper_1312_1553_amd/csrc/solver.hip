@@ -678,7 +678,15 @@ __global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag) {
   reduce_parts(part, nb, 1, red);
   if (threadIdx.x) return;
   c->dgn = sqrt(red[0] / c->dxx);
-  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax) c->ddone = 1;
+  if (c->dgn < 0.9 * c->dbest) {
+    c->dbest = c->dgn;
+    c->dbest_it = c->dits;
+  }
+  // stall (float only): no 10 % gain for dstall iterations while within 10x of the target, i.e.
+  // at the float residual floor, which can sit above tol q when q is small against ||A||
+  const bool stall = c->dstall > 0 && c->dits - c->dbest_it >= c->dstall && c->dbest <= 10.0 * c->dtol * c->dq;
+  if (stall) c->dstalled = 1;
+  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax || stall) c->ddone = 1;
   post_flag(hflag, c->ddone);
 }
 
@@ -771,10 +779,14 @@ __global__ void c_dacg_next(DevCtl *c, const double *part, int nb) {
   c->dits++;
 }
 
-__global__ void c_dacg_setup(DevCtl *c, double tol, int itmax) {
+__global__ void c_dacg_setup(DevCtl *c, double tol, int itmax, int stall) {
   if (threadIdx.x) return;
   c->dtol = tol;
   c->ditmax = itmax;
+  c->dbest = 1e300;
+  c->dbest_it = 0;
+  c->dstall = stall;
+  c->dstalled = 0;
   c->dits = 0;
   c->ddone = 0;
   c->dinv = 0.0;
@@ -1427,9 +1439,11 @@ void outer_eval(bnx_ctx *C, const double *u, double *Au, double *r, T *uT, T *Au
 }
 
 // ------------------------------------------------------------------ DACG (Sec. 4.1)
-// x (T) holds the normalised start vector; on return x is the DACG iterate (unit norm).
+// x (T) holds the normalised start vector; on return x is the DACG iterate (unit norm).  stall > 0
+// also ends it after that many iterations without a 10 % gain near tol (*stalled is then set).
 template <typename T>
-int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itmax, long long *mvp) {
+int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itmax, long long *mvp, int stall = 0,
+         bool *stalled = nullptr) {
   const Launch L = C->launch();
   DevCtl *c = C->ctl;
   const int n = C->n;
@@ -1437,7 +1451,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   Mat<T> A = C->mat<T>();
   Tri<T> Lf = C->tri<T>(true), Lt = C->tri<T>(false);
   const int nbi = gridn(n);
-  hipLaunchKernelGGL(c_dacg_setup, dim3(1), dim3(64), 0, C->st, c, tol, itmax);
+  hipLaunchKernelGGL(c_dacg_setup, dim3(1), dim3(64), 0, C->st, c, tol, itmax, stall);
   launch_fill<T>(C->st, n, w.d, T(0));  // no previous direction: the first step is d = -h
   // Ax
   launch_spmv<T>(L, A, w.x, w.Ax, 0, VList<T>{}, 0, VList<T>{}, nullptr, nullptr);
@@ -1483,6 +1497,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
   // the last (gated) scale of x was skipped after convergence: x holds the scaled iterate
   *mvp += h.dits;
+  if (stalled) *stalled = h.dstalled != 0;
   return h.dits;
 }
 
@@ -1792,8 +1807,22 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
       S.dacg_its[j] = dacg<double>(C, *w64, j, Qt64, o.tol, o.itmax_dacg, &mvp);
       HIPCHK(hipMemcpyAsync(u, w64->x, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
     } else {
-      S.dacg_its[j] = dacg<T>(C, w, j, QtT, alone ? o.tol : o.tol_dacg, o.itmax_dacg, &mvp);
+      bool stalled = false;
+      S.dacg_its[j] = dacg<T>(C, w, j, QtT, alone ? o.tol : o.tol_dacg, o.itmax_dacg, &mvp, fp64 ? 0 : kDacgStall,
+                              &stalled);
       launch_cast<T, double>(C->st, n, w.x, u);
+      if (stalled) {
+        // the float iterate stopped gaining at its residual floor, above tau_DACG q: the double
+        // DACG takes it from there to tau_DACG
+        if (!w64) {
+          w64.reset(new Work<double>);
+          make_work<double>(C, *w64, 0, 0);
+        }
+        cgs2_normalize(C, u, tmp, j, Qt64);
+        HIPCHK(hipMemcpyAsync(w64->x, u, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+        S.dacg_its[j] += dacg<double>(C, *w64, j, Qt64, o.tol_dacg, std::max(0, o.itmax_dacg - S.dacg_its[j]), &mvp);
+        HIPCHK(hipMemcpyAsync(u, w64->x, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
+      }
     }
     S.mvp_dacg += mvp;
     C->sync();

@@ -277,6 +277,28 @@ def test_solve_matches_oracle(oracle_mod, name, p):
     S.close()
 
 
+def test_mixed_solve_float_dacg_floor(oracle_mod):
+    """Shifted graph Laplacian, theta = 1e-4 against ||A|| ~ 50: the fp32 DACG residual floor sits near
+    tau_DACG theta, where the float DACG hands over to the double one instead of running to its cap.
+    Both precisions must still match the oracle's eigenvalues and reach the outer tolerance."""
+    A = mats()["rgg_60000"]
+    p = 4
+    x0 = W.initial_block(A.n, p, 0)
+    ev_o, V_o, st_o, _ = oracle_mod.solve(A, p, x0=x0)
+    assert all(st_o["converged"])
+    S = solver_for(A)
+    S.factor()
+    for prec in (FP64, MIXED):
+        say("case float-floor solve rgg_60000", prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        say("  stats", st)
+        assert st["status"] == 0
+        assert max(st["dacg_its"]) < 5000
+        np.testing.assert_allclose(ev.numpy(), ev_o, rtol=1e-10)
+        check_pairs(A, ev.numpy(), host(V), 1e-8)
+    S.close()
+
+
 def test_solve_bad_calls():
     A = mats()["laplace2d_32"]
     S = solver_for(A)
