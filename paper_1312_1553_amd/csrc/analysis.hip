@@ -3,6 +3,7 @@
 // solves.  Index work only; the factorisation itself runs on the device.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -173,6 +174,17 @@ bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S) {
   S.nlev = 0;
   for (int i = 0; i < n; i++) S.nlev = std::max(S.nlev, S.level[i] + 1);
   return fits && 4 * S.nlev <= 3 * nlev0;
+}
+
+bool compress_both(const Analysis &an, bool split, SolveSys &Sf, SolveSys &Sb) {
+  if (compress_system(an, true, kNRC, Sf) && compress_system(an, false, kNRC, Sb)) return true;
+  if (!split) return false;
+  // rows beyond kNRC dependencies run as chains of virtual rows; the substitution must still
+  // halve the levels without growing the entries much (on 27-point elasticity blocks it grows
+  // them 2.5x and the chains lengthen the critical path instead)
+  const long long cap = (3LL * an.nnzL) / 2;
+  return compress_system(an, true, INT_MAX, Sf) && compress_system(an, false, INT_MAX, Sb) && Sf.nnz <= cap &&
+         Sb.nnz <= cap;
 }
 
 void analyse(Analysis &an) {
@@ -527,6 +539,8 @@ void block_schedule(const Analysis &an, bool lower, const std::vector<int> &rows
     lx[i] = l;
   }
   auto owner = [&](int it) { return it < n ? it : vown[it - n]; };
+  bs.item_levels = 0;
+  for (int it = 0; it < nitem; it++) bs.item_levels = std::max(bs.item_levels, lx[it] + 1);
   bs.n = n;
   bs.nr = nr;
   bs.nblocks = nb;

@@ -92,6 +92,7 @@ struct Levels {
 // slice_ptr[s] + 64 (e - kNR) + l (ELL padding: ref INT_MIN, valmap -1).
 constexpr int kNR = 4;   // dependency slots per row in registers (block solve)
 constexpr int kNRC = 6;  // the same for level-compressed systems
+constexpr int kNRW = 8;  // wide rows (split schedules of factors with many dependencies per row)
 constexpr int kLongSlice = 1 << 30;  // flag in cnt: the rank's slice has rows longer than kNR
 // LDS values per block (rows + imports + the zero slot): 159 KiB of the 160 KiB of a CU.
 constexpr int kLdsCap64 = 20352;
@@ -105,6 +106,7 @@ struct BlockSched {
   int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;
   int nr = kNR;                // dependency slots per rank (kNR or kNRC)
   int max_local_levels = 0, max_lds = 0;
+  int item_levels = 0;          // levels of the item graph (rows and virtual rows)
   std::vector<int> bptr;       // nblocks+1: first (padded) rank of each block
   std::vector<int> brows;      // nblocks: LDS rows of each block (its rows, then their virtual rows)
   std::vector<int> nreal;      // nblocks: rows of each block that are rows of the matrix
@@ -155,6 +157,9 @@ struct SolveSys {
 // rounding).  Returns false, leaving S unusable, when the levels do not drop below
 // 3/4 or a row would have more than maxdeps dependencies.
 bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S);
+// The two compressed systems the fp32 solves use, when level-pair substitution pays: every row
+// within kNRC dependencies, or (split schedules) longer rows with at most 1.5x the factor's entries.
+bool compress_both(const Analysis &an, bool split, SolveSys &Sf, SolveSys &Sb);
 // Level sets from per-row levels.
 void levels_from(int n, const std::vector<int> &lev, Levels &L);
 // Register slots of the block solve for the two systems of an analysis: 3 when no row of

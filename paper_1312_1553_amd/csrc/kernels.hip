@@ -794,20 +794,24 @@ void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, 
 
 template <typename T, int CAP>
 static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
-  // three-slot schedules (no row longer than three) and level-compressed systems (kNRC slots,
-  // no row longer than kNRC) need no general path
-  if (F.blk.nr == 3)
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, 3>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
-                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
-  else if (F.blk.nr == kNRC)
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, kNRC>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
-                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
-  else if (F.blk.ell > 0)
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, true, kNR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
-                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
-  else
-    hipLaunchKernelGGL((k_trsv_blk<T, CAP, false, kNR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,
-                       reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate);
+#define BNX_BLK(LONG, NR)                                                                                         \
+  hipLaunchKernelGGL((k_trsv_blk<T, CAP, LONG, NR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,    \
+                     reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate)
+  // three-slot schedules (no row longer than three), level-compressed systems (kNRC slots)
+  // and wide split schedules (kNRW slots, float only: eight double slots spill registers)
+  // have no row beyond their slots and need no general path
+  if (F.blk.nr == 3) {
+    BNX_BLK(false, 3);
+  } else if (F.blk.nr == kNRC) {
+    BNX_BLK(false, kNRC);
+  } else if (sizeof(T) == 4 && F.blk.nr == kNRW) {
+    if constexpr (sizeof(T) == 4) BNX_BLK(false, kNRW);
+  } else if (F.blk.ell > 0) {
+    BNX_BLK(true, kNR);
+  } else {
+    BNX_BLK(false, kNR);
+  }
+#undef BNX_BLK
 }
 
 template <typename T>

@@ -2263,14 +2263,19 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   HIPCHK(hipMemcpyAsync(C->mapLt, a.mapLt.data(), sizeof(int) * nnzL, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levL, a.levL.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
   HIPCHK(hipMemcpyAsync(C->levLt, a.levLt.rows.data(), sizeof(int) * n, hipMemcpyHostToDevice, C->st));
-  // Level-pair substitution (compress_system) when it shortens both dependency chains below
-  // 3/4 and keeps every row within kNRC dependencies: the solves then run the two compressed
-  // systems, whose values finish_factor derives from the factor's.
+  // Long rows (more than nr dependencies) through chains of virtual partial-sum rows, so
+  // every row of the block solve takes its branch-free path
+  bool split = true;
+  if (const char *e = getenv("BNX_SPLIT_LONG")) split = atoi(e) != 0;  // tuning override
+  // Level-pair substitution (compress_both) when it shortens both dependency chains below
+  // 3/4 and keeps every row within kNRC dependencies, or, with split schedules, grows the
+  // entries by at most half: the fp32 solves then run the two compressed systems, whose
+  // values finish_factor derives from the factor's.
   bool lps = true;
   if (const char *e = getenv("BNX_LPS")) lps = atoi(e) != 0;  // tuning override
   {
     SolveSys Sf, Sb;
-    C->lps = lps && compress_system(a, true, kNRC, Sf) && compress_system(a, false, kNRC, Sb);
+    C->lps = lps && compress_both(a, split, Sf, Sb);
     if (C->lps) {
       Analysis &S = C->anS;
       S = Analysis{};
@@ -2312,10 +2317,6 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
       C->sync();  // host vectors go out of scope
     }
   }
-  // Long rows (more than nr dependencies) through chains of virtual partial-sum rows, so
-  // every row of the block solve takes its branch-free path
-  bool split = true;
-  if (const char *e = getenv("BNX_SPLIT_LONG")) split = atoi(e) != 0;  // tuning override
   for (int pr = 0; pr < 2; pr++) {
     std::vector<int> prow, pstart;
     // Block size target: larger blocks cross fewer block boundaries, smaller ones
@@ -2324,7 +2325,10 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     // (their levels hold twice the rows: 256 blocks beat 128).
     const bool cmp = C->lps && pr == 1;  // FP32 schedules of the compressed systems
     const Analysis &sa = cmp ? C->anS : a;
-    const int nr = slots_for(sa, cmp);
+    int nr = slots_for(sa, cmp);
+    if (const char *e = getenv("BNX_NR"))  // tuning override: slots of the uncompressed split schedules
+      if (split && !cmp && nr > 3 && (atoi(e) == kNR || atoi(e) == kNRC || (atoi(e) == kNRW && pr == 1)))
+        nr = atoi(e);
     int cap = pr == 0 ? kBlkTarget64 : (cmp ? kBlkTarget32C : kBlkTarget32);
     if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
       cap = atoi(e);

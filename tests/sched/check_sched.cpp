@@ -185,7 +185,7 @@ static double emulate(const Analysis &sys, bool lower, const std::vector<int> &r
   return err / scale;
 }
 
-static void run(Analysis &an, int cap, const char *name, bool split, bool lps) {
+static void run(Analysis &an, int cap, const char *name, bool split, bool lps, int nr_force = 0) {
   analyse(an);
   const int n = an.n;
   // a well-conditioned lower-triangular factor on the pattern (diagonal dominant)
@@ -212,10 +212,10 @@ static void run(Analysis &an, int cap, const char *name, bool split, bool lps) {
   int nr = kNR;
   if (lps) {
     SolveSys Sf, Sb;
-    const bool okf = compress_system(an, true, kNRC, Sf), okb = compress_system(an, false, kNRC, Sb);
-    printf("%s: level-pair substitution %s (levels %d -> %d, %d -> %d)\n", name, okf && okb ? "applies" : "rejected",
-           an.levL.nlev, Sf.nlev, an.levLt.nlev, Sb.nlev);
-    if (!(okf && okb)) return;
+    const bool ok = compress_both(an, split, Sf, Sb);
+    printf("%s: level-pair substitution %s (levels %d -> %d, %d -> %d, entries %d -> %d)\n", name,
+           ok ? "applies" : "rejected", an.levL.nlev, Sf.nlev, an.levLt.nlev, Sb.nlev, an.nnzL, Sf.nnz);
+    if (!ok) return;
     cs.n = n;
     cs.Lrp = Sf.rp;
     cs.Lci = Sf.ci;
@@ -241,13 +241,13 @@ static void run(Analysis &an, int cap, const char *name, bool split, bool lps) {
       // levels strictly increase along every dependency of the compressed system
       for (int i = 0; i < n; i++) {
         const int a = d == 0 ? S.rp[i] : S.rp[i] + 1, z = d == 0 ? S.rp[i + 1] - 1 : S.rp[i + 1];
-        CHECK(z - a <= kNRC, "compressed row longer than kNRC");
+        CHECK(split || z - a <= kNRC, "compressed row longer than kNRC");
         for (int e = a; e < z; e++) CHECK(S.level[S.ci[e]] < S.level[i], "compressed level order");
       }
     }
     sys = &cs;
   }
-  nr = slots_for(*sys, lps);
+  nr = nr_force ? nr_force : slots_for(*sys, lps);
   std::vector<int> rows, pstart;
   if (!partition_rows(*sys, cap, rows, pstart, split, nr, lps ? &an : nullptr)) {
     printf("%s: partition infeasible\n", name);
@@ -279,11 +279,23 @@ int main(int argc, char **argv) {
       Analysis a;
       grid(8, 3, true, a);
       run(a, 900, "27-point 8^3 x 3 dof", split, lps);
+      if (split && !lps)  // the other slot counts of split schedules
+        for (int nrf : {kNRC, kNRW}) {
+          Analysis b;
+          grid(8, 3, true, b);
+          run(b, 900, "27-point 8^3 x 3 dof", split, lps, nrf);
+        }
     }
     if (want("graph")) {
       Analysis a;
       geometric(4000, 0.03, 3, a);
       run(a, 900, "geometric graph 4000", split, lps);
+      if (split && !lps)
+        for (int nrf : {kNRC, kNRW}) {
+          Analysis b;
+          geometric(4000, 0.03, 3, b);
+          run(b, 900, "geometric graph 4000", split, lps, nrf);
+        }
     }
   }
   printf("bad %d\n", bad);

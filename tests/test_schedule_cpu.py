@@ -34,9 +34,13 @@ def test_block_schedules_emulated(checker, case):
     assert "bad 0" in r.stdout
 
 
-def test_level_pair_substitution_applies_to_grids_only(checker):
+def test_level_pair_substitution_rule(checker):
+    """Grids fit six dependencies per substituted row; the geometric graph's substituted rows are longer but add
+    under half the entries (chains of virtual rows take the long ones); 27-point elasticity blocks would double
+    them, so they keep the factor's own system."""
     r = subprocess.run([checker, "all"], capture_output=True, text=True, timeout=300)
     out = r.stdout
-    assert "7-point 24^3: level-pair substitution applies (levels 70 -> 36, 70 -> 36)" in out
+    assert "7-point 24^3: level-pair substitution applies (levels 70 -> 36, 70 -> 36, entries 53568 -> 71748)" in out
     assert "27-point 8^3 x 3 dof: level-pair substitution rejected" in out
-    assert "geometric graph 4000: level-pair substitution rejected" in out
+    assert "geometric graph 4000: level-pair substitution applies (levels 338 -> 170, 338 -> 170" in out
+    assert "geometric graph 4000 split lps forward" in out
