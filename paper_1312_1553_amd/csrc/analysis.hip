@@ -83,7 +83,7 @@ int slots_for(const Analysis &sys, bool compressed) {
   return compressed ? kNRC : kNR;
 }
 
-bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S) {
+bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S, long long max_entries) {
   const int n = an.n;
   const std::vector<int> &rp = lower ? an.Lrp : an.Ltrp;
   const std::vector<int> &ci = lower ? an.Lci : an.Ltci;
@@ -95,6 +95,35 @@ bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S) {
   };
   auto diag = [&](int i) { return lower ? rp[i + 1] - 1 : rp[i]; };
   S = SolveSys{};
+  {
+    // counting pass (no recipes): reject early when a row exceeds maxdeps or the entries exceed
+    // max_entries, before the recipes of a system that would be discarded are built
+    std::vector<int> mark(n, -1);
+    long long entries = 0;
+    for (int i = 0; i < n; i++) {
+      int e0, e1, cnt = 0;
+      deps(i, e0, e1);
+      const bool even = (lev[i] & 1) == 0;
+      auto add = [&](int k) {
+        if (mark[k] != i) {
+          mark[k] = i;
+          cnt++;
+        }
+      };
+      for (int e = e0; e < e1; e++) {
+        const int j = ci[e];
+        if (even && (lev[j] & 1) == 1) {
+          int f0, f1;
+          deps(j, f0, f1);
+          for (int f = f0; f < f1; f++) add(ci[f]);
+        } else {
+          add(j);
+        }
+      }
+      entries += cnt + 1;
+      if (cnt > maxdeps || entries > max_entries) return false;
+    }
+  }
   S.n = n;
   S.rp.assign(n + 1, 0);
   S.mp.assign(n + 1, 0);
@@ -183,8 +212,7 @@ bool compress_both(const Analysis &an, bool split, SolveSys &Sf, SolveSys &Sb) {
   // halve the levels without growing the entries much (on 27-point elasticity blocks it grows
   // them 2.5x and the chains lengthen the critical path instead)
   const long long cap = (3LL * an.nnzL) / 2;
-  return compress_system(an, true, INT_MAX, Sf) && compress_system(an, false, INT_MAX, Sb) && Sf.nnz <= cap &&
-         Sb.nnz <= cap;
+  return compress_system(an, true, INT_MAX, Sf, cap) && compress_system(an, false, INT_MAX, Sb, cap);
 }
 
 void analyse(Analysis &an) {

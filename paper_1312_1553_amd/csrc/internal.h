@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -155,8 +156,9 @@ struct SolveSys {
 // level replaced by that row's own equation, so it depends on rows further down and
 // the chain of dependent levels roughly halves (the solution is unchanged up to
 // rounding).  Returns false, leaving S unusable, when the levels do not drop below
-// 3/4 or a row would have more than maxdeps dependencies.
-bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S);
+// 3/4, a row would have more than maxdeps dependencies, or the system more than
+// max_entries entries (diagonal included).
+bool compress_system(const Analysis &an, bool lower, int maxdeps, SolveSys &S, long long max_entries = LLONG_MAX);
 // The two compressed systems the fp32 solves use, when level-pair substitution pays: every row
 // within kNRC dependencies, or (split schedules) longer rows with at most 1.5x the factor's entries.
 bool compress_both(const Analysis &an, bool split, SolveSys &Sf, SolveSys &Sb);
