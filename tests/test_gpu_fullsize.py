@@ -86,7 +86,17 @@ def test_fullsize_spmv_and_ic_solves(oracle_mod, name):
         say(f"  solve {which}: fp64 {e64:.2e} fp32 {e32:.2e}")
         assert e64 < 1e-11, (which, e64)  # observed <= 5e-13 (C3), 1e-15 (C1, C2)
         assert e32 < 1e-5, (which, e32)  # observed <= 3.5e-7 on these three matrices
+    # which systems the substitutions run: FP64 the factor's own; FP32 the level-compressed ones on the grid
+    # (rows within six dependencies) and the graph (longer rows as virtual-row chains), not on elasticity
+    for prec in (FP64, MIXED):
+        _, _, st = S.solve(1, precision=prec, itmax=1, tol_dacg=0.5)
+        assert (st["levels_L"], st["levels_Lt"]) == LEVELS[name][prec], (name, prec)
     S.close()
+
+
+LEVELS = {"c1_diffusion3d_100": {FP64: (298, 298), MIXED: (150, 150)},
+          "c2_elasticity_50": {FP64: (1041, 1041), MIXED: (1041, 1041)},
+          "c3_rgg_500k": {FP64: (2835, 2835), MIXED: (1418, 1418)}}
 
 
 def test_fullsize_c1_solve_matches_oracle():
