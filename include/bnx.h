@@ -179,6 +179,12 @@ bnx_status bnx_factor_info(const bnx_ctx *ctx, long long *nnz_L, double *fill, i
  * was not close enough for Newton (Sec. 4.1): DACG is resumed from the current
  * iterate to 0.1 ||r||/theta (kept within [tol, tol_dacg]), the BFGS history is
  * restarted and Newton continues; at most 5 such returns per pair.
+ * Mixed precision (BNX_MIXED) also hands work to double precision where float
+ * rounding sets a floor: the float DACG ends when its residual has not dropped
+ * by 10 % for 200 iterations within 10x of tol_dacg q, and the double DACG
+ * continues from its iterate to tol_dacg; a pair whose outer residual is below
+ * 1e-7 theta and has not improved by 10 % for three outer steps is finished by
+ * the double DACG to tol.
  * Returns BNX_OK, or BNX_NOT_CONVERGED with results still written.
  * Errors: BNX_E_STATE (no factor), BNX_E_ARG, BNX_E_BREAKDOWN, BNX_E_HIP.
  * The eigenpairs are kept in the context for bnx_backward.
