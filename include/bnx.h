@@ -177,7 +177,7 @@ bnx_status bnx_factor_info(const bnx_ctx *ctx, long long *nnz_L, double *fill, i
  * When the Newton phase of a pair stalls (a PCG solve takes no step, or the
  * outer residual fails to drop below 0.9x in two consecutive steps) the start
  * was not close enough for Newton (Sec. 4.1): DACG is resumed from the current
- * iterate to 0.1 ||r||/theta (kept within [tol, tol_dacg]), the BFGS history is
+ * iterate to 0.005 ||r||/theta (kept within [tol, tol_dacg]), the BFGS history is
  * restarted and Newton continues; at most 5 such returns per pair.
  * Mixed precision (BNX_MIXED) also hands work to double precision where float
  * rounding sets a floor: the float DACG ends when its residual has not dropped

@@ -39,7 +39,7 @@
  *   when the Newton phase stalls (a PCG solve takes no step, or the outer
  *   residual fails to drop below 0.9x in two consecutive steps) the start was
  *   not close enough in the sense of Sec. 4.1: DACG is resumed from the current
- *   iterate to 0.1 ||r||/theta (within [tol, tol_DACG]), the BFGS history is
+ *   iterate to 0.005 ||r||/theta (within [tol, tol_DACG]), the BFGS history is
  *   restarted, and Newton continues (at most 5 times per eigenpair).
  */
 #include <math.h>
@@ -856,7 +856,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
             k++;
             if ((its == 0 || slow >= 2) && restarts < 5 && rn > o->tol * theta && k < o->itmax) {
                 /* return to DACG from the current iterate with a tighter tolerance, restart the BFGS history */
-                double t2 = 0.1 * rn / theta;
+                double t2 = 0.005 * rn / theta;
                 if (t2 > o->tol_dacg) t2 = o->tol_dacg;
                 if (t2 < o->tol) t2 = o->tol;
                 double td2 = now_s();

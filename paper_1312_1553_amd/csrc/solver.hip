@@ -1981,7 +1981,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
         // the start was not close enough (Sec. 4.1): resume DACG from u with a tighter tolerance,
         // restart the BFGS history, then continue Newton
         const double td2 = now_s();
-        const double t2 = floor ? o.tol : std::min(o.tol_dacg, std::max(o.tol, 0.1 * rn / theta));
+        const double t2 = floor ? o.tol : std::min(o.tol_dacg, std::max(o.tol, 0.005 * rn / theta));
         long long mvp2 = 0;
         if (fp64) {
           launch_cast<double, T>(C->st, n, u, w.x);

@@ -1,7 +1,7 @@
 """Write the FP64 oracle's eigenvalues for a workload into tests/golden (calls only oracle/ and the
 seeded generators; nothing here touches the HIP library).
 
-    python tests/golden/make_oracle_evals.py diffusion3d 100 10   # the n = 10^6 headline case (~12 min, 1 core)
+    python tests/golden/make_oracle_evals.py diffusion3d 100 10   # the n = 10^6 headline case (~16 min, 1 core)
 """
 import json
 import os
