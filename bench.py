@@ -133,8 +133,8 @@ def main():
                          "preconditioner; Table 2 defaults are 30,1e-2)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              f"DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is built and measured on a "
+              f"single GPU, and sharding it across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
