@@ -106,9 +106,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=100, help="cells per side (100 = the headline n = 10^6 case)")
     ap.add_argument("--p", type=int, default=0, help="eigenpairs (default: the workload's, 10 for the headline)")
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4"], default="c1",
-                    help="c1: 3-D diffusion (the headline); c2: Q1 elasticity 50^3 elements, p = 20; c3: geometric "
-                         "graph Laplacian, 500k nodes, p = 10; c4: 64^3 diffusion, p = 5, solve + backward of "
+    ap.add_argument("--workload", choices=["diffusion100", "elasticity50", "rgg500k", "diffusion64grad"],
+                    default="diffusion100",
+                    help="diffusion100: 3-D diffusion on --grid^3 cells, p = 10 (the headline); elasticity50: Q1 "
+                         "elasticity on 50^3 elements, p = 20; rgg500k: geometric graph Laplacian, 500k nodes, p = 10; "
+                         "diffusion64grad: 64^3 diffusion, p = 5, solve + backward of "
                          "sum(lambda) + sum_j w_j v_1[j]^2")
     ap.add_argument("--trsv-mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -146,16 +148,16 @@ def main():
     N = args.grid
     t0 = time.time()
     wgrad = None
-    if args.workload == "c2":
+    if args.workload == "elasticity50":
         p, A, wname = args.p or 20, W.elasticity_q1(50, seed=2), "elasticity_q1_50^3_lognormal_seed2"
-    elif args.workload == "c3":
+    elif args.workload == "rgg500k":
         p, A, wname = args.p or 10, W.rgg_laplacian(500_000, seed=3), "rgg_laplacian_500k_seed3_rcm"
-    elif args.workload == "c4":
+    elif args.workload == "diffusion64grad":
         pat, logk, wgrad = W.diffusion_grad_case(64, seed=4)
         p, A, wname = args.p or 5, pat.csr(logk), "diffusion3d_64^3_seed4_solve_and_backward"
     else:
         p, A, wname = args.p or 10, W.diffusion_3d(N, seed=1), f"diffusion3d_{N}^3_lognormal_seed1"
-    if args.workload != "c1":
+    if args.workload != "diffusion100":
         args.no_cpu_baseline = True  # the oracle sample is defined on the headline workload
     x0 = W.initial_block(A.n, p, 0)
     print(f"[bench] workload {wname} n={A.n} nnz={A.nnz} p={p} built in {time.time() - t0:.1f}s", flush=True)
@@ -201,7 +203,7 @@ def main():
             S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
                                  kmax=args.kmax, tol_dacg=args.tol_dacg)
-            if wgrad is not None:  # C4: the backward of the loss through the same solve
+            if wgrad is not None:  # the backward of the loss through the same solve
                 GV = torch.zeros_like(V)
                 GV[0] = 2 * wgrad_d * V[0]
                 S.backward(np.ones(p), GV)
@@ -256,7 +258,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         oracle.build()
-        Ac = A if args.cpu_sample_grid == N and args.workload == "c1" else W.diffusion_3d(args.cpu_sample_grid, seed=1)
+        Ac = A if args.cpu_sample_grid == N and args.workload == "diffusion100" else W.diffusion_3d(args.cpu_sample_grid, seed=1)
         x0c = W.initial_block(Ac.n, 1, 0)
         t0 = time.perf_counter()
         ev_o, V_o, st_o, _ = oracle.solve(Ac, 1, x0=x0c)
@@ -298,7 +300,7 @@ def main():
                                                        / np.array(fp64["evals"]))),
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": counter_traffic(kname, N) if args.workload == "c1" else None,
+                     "traffic": counter_traffic(kname, N) if args.workload == "diffusion100" else None,
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                      "levels": levels,
                      "limiter": ("latency: a chain of %d dependent levels" % levels) if kname.startswith("trsv")

@@ -1,13 +1,13 @@
 """Parity at the full sizes of the benchmark configurations, through the C-ABI, in the launch
 configuration bench.py times (default block schedule).
 
-* Kernels (SpMV, both IC(0) triangular solves) on the full C1 (100^3 diffusion, n = 10^6), C2 (Q1
-  elasticity, 50^3 elements, n = 390,150) and C3 (500k-node geometric graph Laplacian) matrices,
+* Kernels (SpMV, both IC(0) triangular solves) on the full 100^3 diffusion (n = 10^6), Q1 elasticity
+  (50^3 elements, n = 390,150) and 500k-node geometric graph Laplacian matrices,
   compared element by element with the FP64 oracle, which runs these single steps in well under a
   second.
-* The full C1 eigensolve (p = 10) against the oracle's eigenvalues stored in tests/golden (written by
+* The full 100^3 diffusion eigensolve (p = 10) against the oracle's eigenvalues stored in tests/golden (written by
   tests/golden/make_oracle_evals.py, which calls only oracle/), plus residual and orthonormality.
-* The C4 backward at 64^3 through properties that hold at any size, and against central finite
+* The differentiation case's backward at 64^3 through properties that hold at any size, and against central finite
   differences of the oracle's own solves at 16^3.
 """
 import json
@@ -53,9 +53,9 @@ def oracle_mod():
 
 
 FULL = {
-    "c1_diffusion3d_100": lambda: W.diffusion_3d(100, seed=1),
-    "c2_elasticity_50": lambda: W.elasticity_q1(50, seed=2),
-    "c3_rgg_500k": lambda: W.rgg_laplacian(500_000, seed=3),
+    "diffusion3d_100": lambda: W.diffusion_3d(100, seed=1),
+    "elasticity_50": lambda: W.elasticity_q1(50, seed=2),
+    "rgg_500k": lambda: W.rgg_laplacian(500_000, seed=3),
 }
 
 
@@ -84,7 +84,7 @@ def test_fullsize_spmv_and_ic_solves(oracle_mod, name):
         bnx.bnx_ic_apply(S.h, MIXED, which, dev(x), y)
         e32 = np.abs(host(y) - refs[which]).max() / np.abs(refs[which]).max()
         say(f"  solve {which}: fp64 {e64:.2e} fp32 {e32:.2e}")
-        assert e64 < 1e-11, (which, e64)  # observed <= 5e-13 (C3), 1e-15 (C1, C2)
+        assert e64 < 1e-11, (which, e64)  # observed <= 5e-13 (graph), 1e-15 (diffusion, elasticity)
         assert e32 < 1e-5, (which, e32)  # observed <= 3.5e-7 on these three matrices
     # which systems the substitutions run: FP64 the factor's own; FP32 the level-compressed ones on the grid
     # (rows within six dependencies) and the graph (longer rows as virtual-row chains), not on elasticity
@@ -94,12 +94,12 @@ def test_fullsize_spmv_and_ic_solves(oracle_mod, name):
     S.close()
 
 
-LEVELS = {"c1_diffusion3d_100": {FP64: (298, 298), MIXED: (150, 150)},
-          "c2_elasticity_50": {FP64: (1041, 1041), MIXED: (1041, 1041)},
-          "c3_rgg_500k": {FP64: (2835, 2835), MIXED: (1418, 1418)}}
+LEVELS = {"diffusion3d_100": {FP64: (298, 298), MIXED: (150, 150)},
+          "elasticity_50": {FP64: (1041, 1041), MIXED: (1041, 1041)},
+          "rgg_500k": {FP64: (2835, 2835), MIXED: (1418, 1418)}}
 
 
-def test_fullsize_c1_solve_matches_oracle():
+def test_fullsize_diffusion100_solve_matches_oracle():
     g = json.load(open(os.path.join(GOLDEN, "oracle_evals_diffusion3d_100_p10.json")))
     p = g["p"]
     A = W.diffusion_3d(100, seed=1)
@@ -109,7 +109,7 @@ def test_fullsize_c1_solve_matches_oracle():
     ref = np.array(g["evals"])
     M = A.to_scipy()
     for prec in (FP64, MIXED):
-        say("case fullsize C1 solve", prec)
+        say("case fullsize diffusion 100^3 solve", prec)
         ev, V, st = S.solve(p, precision=prec, x0=x0)
         ev = ev.numpy()
         assert st["status"] == 0 and all(st["converged"][:p])
@@ -127,7 +127,7 @@ def test_fullsize_c1_solve_matches_oracle():
     S.close()
 
 
-def test_fullsize_c4_backward_properties():
+def test_fullsize_diffusion64_backward_properties():
     """64^3, p = 5, loss = sum(lambda) + sum_j w_j v_1[j]^2.  Scaling A leaves the eigenvectors unchanged and
     scales the eigenvalues, so <dL/dvals, vals> = sum(lambda); the eigenvalue part of the gradient is
     sum_i v_i[a] v_i[b] on every stored entry (checked on a sample); the gradient is symmetric."""
@@ -144,7 +144,7 @@ def test_fullsize_c4_backward_properties():
     tkey = cols * A.n + rows
     tpos = np.searchsorted(key, tkey)
     for prec in (FP64, MIXED):
-        say("case fullsize C4 backward", prec)
+        say("case fullsize diffusion 64^3 backward", prec)
         ev, V, st = S.solve(p, precision=prec, x0=x0, tol=1e-10)
         assert st["status"] == 0
         ev = ev.numpy().astype(np.float64)
@@ -163,7 +163,7 @@ def test_fullsize_c4_backward_properties():
     S.close()
 
 
-def test_c4_backward_vs_oracle_finite_differences(oracle_mod):
+def test_diffusion_backward_vs_oracle_finite_differences(oracle_mod):
     """16^3 (n = 4096), p = 5: directional derivatives of the GPU gradient w.r.t. log k along 8 random
     directions and 8 coordinates against central differences (h = 1e-4) of the oracle's solves at
     tol 1e-12.  The error is measured against the scale of a directional derivative, |grad|_2 |d|_2
@@ -189,7 +189,7 @@ def test_c4_backward_vs_oracle_finite_differences(oracle_mod):
         dirs.append(e)
     fd = [(loss_oracle(logk + h * d) - loss_oracle(logk - h * d)) / (2 * h) for d in dirs]
     for prec in (FP64, MIXED):
-        say("case C4 FD 16^3", prec)
+        say("case backward FD 16^3", prec)
         lkg = torch.tensor(logk, requires_grad=True, device="cuda")
         ev, Vg = EigSolve.apply(pat.values_torch(lkg), S, p, prec, {"tol": 1e-12, "x0": x0})
         loss = ev.sum() + (torch.tensor(w, device="cuda") * Vg[0] ** 2).sum()
@@ -204,11 +204,11 @@ def test_c4_backward_vs_oracle_finite_differences(oracle_mod):
     S.close()
 
 
-def test_fullsize_c1_ict_solves(oracle_mod):
-    """IC(30, 1e-2) (Table 2's lfil and tau_IC) on the full C1 matrix: the host factor installed with its
+def test_fullsize_diffusion100_ict_solves(oracle_mod):
+    """IC(30, 1e-2) (Table 2's lfil and tau_IC) on the full 100^3 diffusion matrix: the host factor installed with its
     own block schedules, L z = b, L^T c = b and both against the oracle's factor."""
     A = W.diffusion_3d(100, seed=1)
-    say("case fullsize C1 ict", A.n, A.nnz)
+    say("case fullsize diffusion 100^3 ict", A.n, A.nnz)
     S = bnx.Solver(A.rowptr, A.col, A.val)
     S.factor(ict=1, lfil=30, tau_ic=1e-2)
     F = oracle_mod.ict(A, 30, 1e-2)
@@ -227,8 +227,8 @@ def test_fullsize_c1_ict_solves(oracle_mod):
 
 
 @pytest.mark.parametrize("kmax", [0, 5])
-def test_fullsize_c1_jd_matches_oracle_evals(kmax):
-    """Jacobi-Davidson (Sec. 6) on the full C1 problem, p = 10, fp64 and mixed: the same eigenvalues as the
+def test_fullsize_diffusion100_jd_matches_oracle_evals(kmax):
+    """Jacobi-Davidson (Sec. 6) on the full 100^3 diffusion problem, p = 10, fp64 and mixed: the same eigenvalues as the
     oracle's DACG-Newton run stored in tests/golden (the eigenpairs do not depend on the outer method),
     residuals by scipy, orthonormality."""
     g = json.load(open(os.path.join(GOLDEN, "oracle_evals_diffusion3d_100_p10.json")))
@@ -240,7 +240,7 @@ def test_fullsize_c1_jd_matches_oracle_evals(kmax):
     ref = np.array(g["evals"])
     M = A.to_scipy()
     for prec in (FP64, MIXED):
-        say("case fullsize C1 jd", kmax, prec)
+        say("case fullsize diffusion 100^3 jd", kmax, prec)
         ev, V, st = S.solve(p, precision=prec, x0=x0, jd=1, kmax=kmax)
         ev = ev.numpy()
         assert st["status"] == 0 and all(st["converged"][:p]) and sum(st["dacg_its"]) == 0
