@@ -216,6 +216,13 @@ static void run(Analysis &an, int cap, const char *name, bool split, bool lps, i
     printf("%s: level-pair substitution %s (levels %d -> %d, %d -> %d, entries %d -> %d)\n", name,
            ok ? "applies" : "rejected", an.levL.nlev, Sf.nlev, an.levLt.nlev, Sb.nlev, an.nnzL, Sf.nnz);
     if (!ok) return;
+    // the counting pass that screens a substitution counts exactly the entries the build writes
+    for (int d = 0; d < 2; d++) {
+      const SolveSys &S = d == 0 ? Sf : Sb;
+      SolveSys T;
+      CHECK(compress_system(an, d == 0, INT_MAX, T, S.nnz) && T.nnz == S.nnz, "entry count admits the system");
+      CHECK(!compress_system(an, d == 0, INT_MAX, T, S.nnz - 1), "entry count one short rejects it");
+    }
     cs.n = n;
     cs.Lrp = Sf.rp;
     cs.Lci = Sf.ci;
