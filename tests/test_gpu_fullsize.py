@@ -127,6 +127,61 @@ def test_fullsize_diffusion100_solve_matches_oracle():
     S.close()
 
 
+def test_fullsize_rgg500k_solve_closed_form():
+    """500k-node geometric graph, L + 1e-4 I, p = 10, the benchmark's configuration (level-compressed fp32
+    solves with virtual-row chains): each connected component contributes an eigenvalue of exactly 1e-4
+    (its constant vector), and the graph has more than p components, so every eigenvalue found is 1e-4.
+    The residuals are checked by scipy on the host; orthonormality to 1e-10."""
+    from scipy.sparse.csgraph import connected_components
+    A = W.rgg_laplacian(500_000, seed=3)
+    p = 10
+    M = A.to_scipy()
+    assert connected_components(M, directed=False)[0] > p
+    S = bnx.Solver(A.rowptr, A.col, A.val)
+    S.factor()
+    x0 = torch.as_tensor(W.initial_block(A.n, p, 0)).cuda()
+    for prec in (FP64, MIXED):
+        say("case fullsize rgg 500k solve", prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        ev = ev.numpy()
+        assert st["status"] == 0 and all(st["converged"][:p])
+        say("  max |lambda - 1e-4| / 1e-4", np.abs(ev - 1e-4).max() / 1e-4)
+        # relres <= 1e-8 bounds the eigenvalue error by (1e-8)^2 lambda / gap: far below 1e-10
+        assert np.abs(ev - 1e-4).max() <= 1e-10 * 1e-4
+        Vh = host(V)
+        res = max(np.linalg.norm(M @ Vh[j] - ev[j] * Vh[j]) / ev[j] for j in range(p))
+        assert res <= 1.0e-8 * 1.01, res
+        assert np.abs(Vh @ Vh.T - np.eye(p)).max() < 1e-10
+    S.close()
+
+
+def test_fullsize_elasticity50_solve_properties():
+    """Q1 elasticity on 50^3 elements, p = 20, the benchmark's configuration (six-slot split schedules): both
+    precisions reach the outer tolerance by scipy's residuals on the host, return orthonormal vectors, and agree
+    on the eigenvalues to 1e-10 (each within O(relres^2) of an exact eigenvalue)."""
+    A = W.elasticity_q1(50, seed=2)
+    p = 20
+    M = A.to_scipy()
+    S = bnx.Solver(A.rowptr, A.col, A.val)
+    S.factor()
+    x0 = torch.as_tensor(W.initial_block(A.n, p, 0)).cuda()
+    evs = []
+    for prec in (FP64, MIXED):
+        say("case fullsize elasticity 50 solve", prec)
+        ev, V, st = S.solve(p, precision=prec, x0=x0)
+        ev = ev.numpy()
+        assert st["status"] == 0 and all(st["converged"][:p])
+        assert np.all(np.diff(ev) >= 0) and ev[0] > 0
+        Vh = host(V)
+        res = max(np.linalg.norm(M @ Vh[j] - ev[j] * Vh[j]) / ev[j] for j in range(p))
+        say("  max relres", res)
+        assert res <= 1.0e-8 * 1.01, res
+        assert np.abs(Vh @ Vh.T - np.eye(p)).max() < 1e-10
+        evs.append(ev)
+    assert np.abs(evs[0] - evs[1]).max() / evs[0].max() < 1e-10
+    S.close()
+
+
 def test_fullsize_diffusion64_backward_properties():
     """64^3, p = 5, loss = sum(lambda) + sum_j w_j v_1[j]^2.  Scaling A leaves the eigenvectors unchanged and
     scales the eigenvalues, so <dL/dvals, vals> = sum(lambda); the eigenvalue part of the gradient is
