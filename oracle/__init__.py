@@ -96,6 +96,8 @@ def lib():
         L.or_dacg_apply.argtypes = [C.c_int, _pi, _pi, _pd, _pi, _pi, _pd, C.c_int, _pd, _pd, C.c_double, C.c_int,
                                     _pd, _pd, C.c_int]
         L.or_dacg_apply.restype = C.c_int
+        L.or_window_apply.argtypes = [C.c_int, _pi, _pi, _pd, C.c_int, C.c_int, _pd, _pd, C.c_int, _pd, _pd, _pd]
+        L.or_window_apply.restype = C.c_int
     return _lib
 
 
@@ -215,6 +217,19 @@ def bfgspk(F: Factor, S, R, Q, g):
     return c
 
 
+def window_bfgspk(F: Factor, kmax, S, R, Q, g):
+    """Push the pairs (rows of S, R, in production order) through the k_max window, then Alg. 1 with the pairs
+    it kept.  Returns (c, number kept)."""
+    n = F.n
+    Q = np.zeros((0, n)) if Q is None else np.atleast_2d(Q)
+    S, pS = _d(np.atleast_2d(S)); R, pR = _d(np.atleast_2d(R)); Q, pQ = _d(Q); g, pg = _d(g)
+    c = np.empty(n)
+    kept = lib().or_window_apply(n, F.rowptr.ctypes.data_as(_pi), F.col.ctypes.data_as(_pi),
+                                 F.val.ctypes.data_as(_pd), int(kmax), S.shape[0], pS, pR, Q.shape[0], pQ, pg,
+                                 c.ctypes.data_as(_pd))
+    return c, kept
+
+
 def pcg(A, F: Factor, theta, Q, u, Au, r, S=None, R=None, tol_pcg=1e-2, itmax_pcg=20, tau=1e-8, exit_rule=1,
         xi=0.1):
     """One PCG solve of the correction equation; returns (s, its, reason)."""
@@ -249,7 +264,9 @@ def linesearch(xAx, dAx, dAd, xx, xd, dd):
 
 
 def solve(A, p, x0=None, trace_cap=0, **kw):
-    """DACG-Newton (Alg. 2).  Returns (evals, evecs (p x n), stats dict, trace (ntrace x 8))."""
+    """DACG-Newton (Alg. 2).  Returns (evals, evecs (p x n), stats dict, trace (ntrace x 8)).  Trace rows are
+    outer steps (j, k, theta_k, ||r_k||, s_k^T r_k, ||s_k||^2, theta_{k+1}, PCG its) and, with k = -1, returns to
+    DACG from a stalled Newton phase (j, -1, DACG tolerance, DACG its, theta, ||r|| after, theta, ||r|| before)."""
     from paper_1312_1553_amd.workloads import initial_block
     n = A.n
     if x0 is None:

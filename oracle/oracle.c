@@ -741,6 +741,8 @@ static int jd_pair(const prob *P, const or_opts *o, int j, double *Qm, const dou
  * row j = v_{j+1}) with the first entry above 1e-12 ||v||_inf made positive.
  * trace (optional, trace_cap records of 8 doubles) receives per outer step:
  *   j, k, theta_k, ||r_k||, alpha_k = s_k^T r_k, ||s_k||^2, theta_{k+1}, PCG its;
+ *   per return to DACG from a stalled Newton phase (k recorded as -1):
+ *   j, -1, DACG tolerance, DACG its, theta and ||r|| after, theta and ||r|| before;
  *   with jd = 1, per Rayleigh-Ritz step: j, k, theta, ||r||, dim V, second Ritz value, 0, 0.
  * Returns 0 when every pair converged, 1 if some did not, <0 on errors.
  */
@@ -809,6 +811,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
         for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
         double rn = nrm2(n, r);
         int k = 0, slow = 0, restarts = 0;
+        double t_restart = 0.0; /* DACG time inside the Newton phase: counted in t_dacg only */
         while (o->newton && rn > o->tol * theta && k < o->itmax) {
             int its = 0;
             int why = or_pcg(&P, theta, j + 1, Qm, u, Au, r, W.k, W.S, W.R, W.alpha, o->tol_pcg, o->itmax_pcg,
@@ -860,8 +863,11 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
                 if (t2 > o->tol_dacg) t2 = o->tol_dacg;
                 if (t2 < o->tol) t2 = o->tol;
                 double td2 = now_s();
-                st->dacg_its[j] += or_dacg(&P, j, Qm, u, t2, o->itmax_dacg, xn, NULL, 0, &st->mvp_dacg, work);
-                st->t_dacg += now_s() - td2;
+                int dits = or_dacg(&P, j, Qm, u, t2, o->itmax_dacg, xn, NULL, 0, &st->mvp_dacg, work);
+                st->dacg_its[j] += dits;
+                td2 = now_s() - td2;
+                st->t_dacg += td2;
+                t_restart += td2;
                 copy(n, xn, u);
                 cgs(n, j, Qm, u, z);
                 cgs(n, j, Qm, u, z);
@@ -869,9 +875,14 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
                 W.k = 0;
                 or_spmv(n, rp, ci, v, u, Au);
                 st->mvp_newton++;
+                double theta0 = theta, rn0 = rn;
                 theta = dot(n, u, Au);
                 for (int i = 0; i < n; i++) r[i] = Au[i] - theta * u[i];
                 rn = nrm2(n, r);
+                if (trace && st->ntrace < trace_cap) {
+                    double *T = trace + 8 * (size_t)st->ntrace++;
+                    T[0] = j; T[1] = -1; T[2] = t2; T[3] = dits; T[4] = theta; T[5] = rn; T[6] = theta0; T[7] = rn0;
+                }
                 restarts++;
                 st->dacg_restarts++;
                 slow = 0;
@@ -882,7 +893,7 @@ int or_solve(int n, const int *rp, const int *ci, const double *v, const or_opts
         st->converged[j] = (rn <= o->tol * theta);
         if (!st->converged[j]) allconv = 0;
         lam[j] = theta;
-        st->t_newton += now_s() - tn;
+        st->t_newton += now_s() - tn - t_restart;
     }
 
     /* sort ascending; sign: first entry above 1e-12 ||v||_inf is positive */
@@ -1019,6 +1030,24 @@ int or_pcg_apply(int n, const int *rp, const int *ci, const double *v, const int
     int why = or_pcg(&P, theta, m, Q, u, Au, r, k, S, R, alpha, tol_pcg, itmax_pcg, tau, exit_rule, xi, s, its, work);
     free(work); free(tmp);
     return why;
+}
+
+/* The k_max window (Sec. 4.4) after npush pairs (rows of S and R, in the order they were produced) went
+ * through it, then Alg. 1 with the pairs it kept (for the window-order tests).  Returns how many it kept. */
+int or_window_apply(int n, const int *Lrp, const int *Lci, const double *Lv, int kmax, int npush, const double *S,
+                    const double *R, int m, const double *Q, const double *g, double *c) {
+    size_t N = (size_t)n;
+    double *tmp = malloc(sizeof(double) * N), *w = malloc(sizeof(double) * N);
+    double a[64], z[OR_MAXP + 1];
+    pairs_t W = {0, kmax, n, malloc(sizeof(double) * N * (kmax > 0 ? kmax : 1)),
+                 malloc(sizeof(double) * N * (kmax > 0 ? kmax : 1)), {0}};
+    prob P = {n, NULL, NULL, NULL, Lrp, Lci, Lv, tmp};
+    for (int t = 0; t < npush; t++)
+        pairs_push(&W, S + (size_t)t * N, R + (size_t)t * N, dot(n, S + (size_t)t * N, R + (size_t)t * N));
+    or_bfgspk(&P, W.k, W.S, W.R, W.alpha, m, Q, g, c, w, a, z);
+    int kept = W.k;
+    free(tmp); free(w); free(W.S); free(W.R);
+    return kept;
 }
 
 /* DACG alone (for the monotone-quotient test). */

@@ -306,7 +306,7 @@ def test_newton_trace_identities(oracle_lib):
     A = W.diffusion_3d(6, seed=1)
     ev, Vr, st, tr = oracle_lib.solve(A, 4, trace_cap=1000)
     assert len(tr) > 4
-    for j, k, th, rn, al, sn2, th1, its in tr:
+    for j, k, th, rn, al, sn2, th1, its in tr[tr[:, 1] >= 0]:  # outer steps (k < 0 marks a return to DACG)
         assert al < 0
         pred = th + al / (1 + sn2)
         assert abs(th1 - pred) <= 1e-7 * abs(al) + 1e-14 * th
