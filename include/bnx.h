@@ -206,6 +206,9 @@ bnx_status bnx_solve(bnx_ctx *ctx, const bnx_solve_opts *opts, double *evals, do
  *  preconditioner projected against Q_i, to relative residual tol_adj; in
  *  mixed precision the inner PCG is float and wrapped in double-precision
  *  iterative refinement.
+ * Returns BNX_NOT_CONVERGED, with g_vals still written, when an adjoint solve
+ * ends with its true projected residual (recomputed in double) above
+ * tol_adj ||(I - Q_i Q_i^T) G_i||; bnx_last_error names the pairs.
  * Errors: BNX_E_STATE (no solve since the last factor), BNX_E_ARG.
  */
 bnx_status bnx_backward(bnx_ctx *ctx, const double *g_evals, const double *g_evecs, double *g_vals);

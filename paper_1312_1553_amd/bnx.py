@@ -250,6 +250,9 @@ class Solver:
         self.stream = torch.cuda.current_stream().cuda_stream
         self.h = bnx_create_csr(self.n, self.nnz, self.rowptr, self.col, val, 1, self.stream)
         self.factored = False
+        # bnx_backward differentiates the handle's most recent solve; each solve and each change of values
+        # starts a new generation, so a backward for an older one can be refused instead of answered wrongly
+        self.generation = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -266,6 +269,7 @@ class Solver:
         val = self.torch.as_tensor(val, dtype=self.torch.float64).cuda().contiguous()
         bnx_set_values(self.h, val)
         self.factored = False
+        self.generation += 1
 
     def factor(self, shift0=1e-3, shift_max=1.0, ict=0, lfil=30, tau_ic=1e-2):
         """IC(0) (ict=0) or IC(lfil, tau_ic) (ict=1) initial preconditioner (Sec. 2)."""
@@ -290,6 +294,7 @@ class Solver:
         ev = np.empty(p)
         V = torch.empty((p, self.n), dtype=torch.float64, device="cuda")
         st = Stats()
+        self.generation += 1
         bnx_solve(self.h, o, ev, V, st)
         return torch.from_numpy(ev), V, st.as_dict(p)
 
@@ -314,10 +319,15 @@ def eigsh_autograd():
             ev, V, st = solver.solve(p, precision=precision, **(opts or {}))
             ctx.solver = solver
             ctx.p = p
+            ctx.generation = solver.generation
             return ev.to(vals.device), V
 
         @staticmethod
         def backward(ctx, g_ev, g_V):
+            if ctx.solver.generation != ctx.generation:
+                raise RuntimeError("EigSolve.backward: the Solver has solved again (or changed its values) since this "
+                                   "forward; the library keeps only the latest eigenpairs, so use one Solver per "
+                                   "forward that is differentiated")
             ge = g_ev.detach().double().cpu().numpy() if g_ev is not None else np.zeros(ctx.p)
             gv = ctx.solver.backward(ge, None if g_V is None else g_V.detach())
             return gv, None, None, None, None

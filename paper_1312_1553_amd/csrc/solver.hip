@@ -1839,6 +1839,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     double theta = h.otheta, rn = h.orn;
     std::deque<int> ring;  // chronological slots
     int k = 0, slow = 0, restarts = 0;
+    double t_restart = 0.0;  // DACG time inside the Newton phase: counted in t_dacg only
     double best = rn;  // mixed precision: smallest outer residual so far
     int since_best = 0;
 
@@ -2010,7 +2011,9 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
         slow = 0;
         best = rn;
         since_best = 0;
-        S.t_dacg += now_s() - td2;
+        const double dt2 = now_s() - td2;
+        S.t_dacg += dt2;
+        t_restart += dt2;
       }
     }
     S.outer_its[j] = k;
@@ -2021,7 +2024,7 @@ bnx_status solve_impl(bnx_ctx *C, const bnx_solve_opts &o, double *evals, double
     if (!fp64) launch_cast<double, T>(C->st, n, u, w.Qm + (size_t)j * n);
     launch_cast<double, T>(C->st, n, Au, w.AQm + (size_t)j * n);  // A v_j from the last outer step
     C->sync();
-    S.t_newton += now_s() - t0;
+    S.t_newton += now_s() - t0 - t_restart;
   }
   // ---- sort ascending, fix signs, write outputs
   std::vector<int> idx(p);
@@ -2096,8 +2099,9 @@ double norm2_host(bnx_ctx *C, const double *x) {
   return std::sqrt(C->readctl().bz[0]);
 }
 
+// Returns an empty string, or a description of the adjoint solves that missed tol_adj.
 template <typename T>
-void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev, double *gv) {
+std::string backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev, double *gv) {
   const int n = C->n, p = C->p_last;
   const Launch L = C->launch();
   DevCtl *c = C->ctl;
@@ -2129,8 +2133,9 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
   hipLaunchKernelGGL(k_grad_lambda, dim3(gridn(n)), dim3(kBlock), 0, C->st, n, C->rp, C->ci, p, V, ge, gv);
   if (!g_evecs_dev) {
     C->sync();
-    return;
+    return std::string();
   }
+  std::string missed;
   if (!fp64)
     for (int q = 0; q < p; q++) launch_cast<double, T>(C->st, n, V + (size_t)q * n, w.Qm + (size_t)q * n);
   Mat<double> A64 = C->mat<double>();
@@ -2172,14 +2177,33 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
     P.exit_rule = 0;
     P.eigtest = 0;
     P.sgn = 1.0;
+    // res = rhs - (I-QQ^T)(A eta - lambda eta) in double; returns ||res||
+    auto true_residual = [&]() {
+      launch_spmv<double>(L, A64, eta, Ae, 0, VList<double>{}, 0, VList<double>{}, nullptr, nullptr);
+      hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 1, -C->evals_last[i]);
+      comb<double>(C, tmp, Ae, 1.0, nullptr, eta, scal + 1, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                   nullptr, nullptr);
+      project_out(C, tmp2, tmp, m, Vl, Ae);
+      hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 2, -1.0);
+      comb<double>(C, res, rhs, 1.0, nullptr, tmp2, scal + 2, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
+                   nullptr, nullptr);
+      return norm2_host(C, res);
+    };
+    bool ok = true;
+    double resn = rhs_n;
     if (fp64) {
       P.tol_pcg = C->adj_tol;
       int its = 0, why = 0;
       pcg<T>(C, w, P, (const T *)res, m, Q, AQ, 0, VList<T>{}, VList<T>{}, nullptr, nullptr, (T *)eta, &its, &why);
+      // reason 1: the recurred residual met tol_adj.  After the cap or a breakdown (p^T J p <= 0, which
+      // rounding produces once the residual is at its floor) the true residual decides.
+      if (why != 1) {
+        resn = true_residual();
+        ok = resn <= C->adj_tol * rhs_n;
+      }
     } else {
       // float PCG inside double iterative refinement
       P.tol_pcg = 1e-4;
-      double resn = rhs_n;
       for (int round = 0; round < 40 && resn > C->adj_tol * rhs_n; round++) {
         launch_cast<double, T>(C->st, n, res, w.r);
         int its = 0, why = 0;
@@ -2190,17 +2214,15 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
         comb<double>(C, tmp2, eta, 1.0, nullptr, tmp, scal, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
                      nullptr, nullptr);
         HIPCHK(hipMemcpyAsync(eta, tmp2, sizeof(double) * n, hipMemcpyDeviceToDevice, C->st));
-        // res = rhs - (I-QQ^T)(A eta - lambda eta)
-        launch_spmv<double>(L, A64, eta, Ae, 0, VList<double>{}, 0, VList<double>{}, nullptr, nullptr);
-        hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 1, -C->evals_last[i]);
-        comb<double>(C, tmp, Ae, 1.0, nullptr, eta, scal + 1, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
-                     nullptr, nullptr);
-        project_out(C, tmp2, tmp, m, Vl, Ae);
-        hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 2, -1.0);
-        comb<double>(C, res, rhs, 1.0, nullptr, tmp2, scal + 2, 0, VList<double>{}, nullptr, 0.0, 0, VList<double>{},
-                     nullptr, nullptr);
-        resn = norm2_host(C, res);
+        resn = true_residual();
       }
+      ok = resn <= C->adj_tol * rhs_n;
+    }
+    if (!ok) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "%sadjoint solve of pair %d: residual %.3g > tol_adj %.3g (relative)",
+               missed.empty() ? "" : "; ", i + 1, resn / rhs_n, C->adj_tol);
+      missed += buf;
     }
     // xi += eta; g_vals -= 1/2 (xi v_i^T + v_i xi^T) on the pattern
     hipLaunchKernelGGL(c_set, dim3(1), dim3(1), 0, C->st, scal + 3, 1.0);
@@ -2210,6 +2232,7 @@ void backward_impl(bnx_ctx *C, const double *g_evals, const double *g_evecs_dev,
   }
   DevCtl h = C->readctl();
   if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  return missed;
 }
 
 // ------------------------------------------------------------------ factor
@@ -2916,11 +2939,15 @@ bnx_status bnx_backward(bnx_ctx *C, const double *g_evals, const double *g_evecs
         for (double *q : t) C->release(q);
       }
     } g{C, tmp};
-    if (C->prec_last == BNX_FP64) backward_impl<double>(C, g_evals, GV, gv);
-    else backward_impl<float>(C, g_evals, GV, gv);
+    const std::string missed = C->prec_last == BNX_FP64 ? backward_impl<double>(C, g_evals, GV, gv)
+                                                         : backward_impl<float>(C, g_evals, GV, gv);
     if (!C->device_ptrs) {
       HIPCHK(hipMemcpyAsync(g_vals, gv, sizeof(double) * C->nnz, hipMemcpyDeviceToHost, C->st));
       C->sync();
+    }
+    if (!missed.empty()) {
+      C->err = missed;
+      return BNX_NOT_CONVERGED;
     }
     return BNX_OK;
   });
