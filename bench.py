@@ -184,6 +184,9 @@ def main():
                     help="1: Jacobi-Davidson outer iteration (Sec. 6, m_min 5, m_max 10) with the same PCG as "
                          "correction solver, instead of DACG-Newton")
     ap.add_argument("--kmax", type=int, default=5, help="BFGS window (0: the fixed initial preconditioner)")
+    ap.add_argument("--itmax-pcg", type=int, default=20, help="IMAX_PCG, the PCG iteration cap (Table 2 default 20)")
+    ap.add_argument("--no-kernel-profile", action="store_true",
+                    help="skip the extra instrumented step that gives the per-kernel averages (parameter sweeps)")
     ap.add_argument("--tol-dacg", type=float, default=1e-2,
                     help="DACG tolerance before Newton (Table 2 default 1e-2; the paper uses 0.1 and 0.2 on two matrices)")
     ap.add_argument("--ict", type=str, default="",
@@ -248,13 +251,13 @@ def main():
         for w in range(args.warmup):
             S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
-                                 kmax=args.kmax, tol_dacg=args.tol_dacg)
+                                 kmax=args.kmax, tol_dacg=args.tol_dacg, itmax_pcg=args.itmax_pcg)
             print(f"[bench] warmup {name} {w}: {st['t_dacg'] + st['t_newton']:.3f}s status {st['status']}",
                   flush=True)
         def step():
             S.factor(**fkw)
             ev, V, st = S.solve(p, precision=prec, x0=x0d, newton=args.newton, bfgs_full=args.bfgs_full, jd=args.jd,
-                                 kmax=args.kmax, tol_dacg=args.tol_dacg)
+                                 kmax=args.kmax, tol_dacg=args.tol_dacg, itmax_pcg=args.itmax_pcg)
             if wgrad is not None:  # the backward of the loss through the same solve
                 GV = torch.zeros_like(V)
                 GV[0] = 2 * wgrad_d * V[0]
@@ -275,14 +278,17 @@ def main():
         # one more step with HIP events recorded around every hot-kernel launch on the library's stream: the
         # per-kernel averages of the roofline (the same work as a timed step; its wall time shows the cost of
         # the events)
-        bnx.bnx_set_profiling(S.h, 1)
-        tp = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - tp
-        kt = {kname: bnx.bnx_kernel_time(S.h, kid) for kname, kid in bnx.KERNEL_IDS.items()}
-        bnx.bnx_set_profiling(S.h, 0)
-        print(f"[bench] {name} profiled step: {tp:.3f}s", flush=True)
+        tp = 0.0
+        kt = {kname: (0.0, 0) for kname in bnx.KERNEL_IDS}
+        if not args.no_kernel_profile:
+            bnx.bnx_set_profiling(S.h, 1)
+            tp = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - tp
+            kt = {kname: bnx.bnx_kernel_time(S.h, kid) for kname, kid in bnx.KERNEL_IDS.items()}
+            bnx.bnx_set_profiling(S.h, 0)
+            print(f"[bench] {name} profiled step: {tp:.3f}s", flush=True)
         # residual check on the last step (independent of the library: scipy on the host)
         Vh = V.cpu().numpy()
         M = A.to_scipy()
@@ -307,6 +313,8 @@ def main():
     for kname, (ms, cnt) in mixed["kt"].items():
         if cnt and (best is None or ms > best[1]):
             best = (kname, ms, cnt)
+    if best is None:  # --no-kernel-profile: no per-kernel times, no roofline
+        best = ("none_f64", float("nan"), 1)
     kname, ms, cnt = best
     prec = kname.split("_")[-1]
     per_launch = (spmv_bytes(A.n, A.nnz, vb[prec]) if kname.startswith("spmv")
@@ -344,7 +352,7 @@ def main():
         "config": {"workload": wname, "n": A.n, "nnz": A.nnz, "p": p, "tol": 1e-8,
                    "parallelism": "single GPU", "trsv_mode": args.trsv_mode,
                    "method": ("Jacobi-Davidson" if args.jd else "DACG-Newton" if args.newton else "DACG alone"),
-                   "kmax": args.kmax, "tol_dacg": args.tol_dacg,
+                   "kmax": args.kmax, "itmax_pcg": args.itmax_pcg, "tol_dacg": args.tol_dacg,
                    "preconditioner": f"IC({args.ict})" if args.ict else "IC(0)",
                    "bfgs_update": "eq. (2.1) full" if args.bfgs_full else "eq. (2.2) simplified",
                    "fill_sigma": round(mixed["stats"]["fill"], 4)},

@@ -16,9 +16,12 @@ constexpr int kMaxVec = 80;    // vectors in one kernel argument list
 constexpr int kJdMax = 16;     // largest Jacobi-Davidson search space
 constexpr int kDacgStall = 200;  // float DACG: iterations without a 10 % gain that end it near tau
 #ifndef BNX_NBMAX
-#define BNX_NBMAX 2048
+#define BNX_NBMAX 1024
 #endif
-constexpr int kNBMax = BNX_NBMAX;  // blocks of a streaming kernel (partials per dot)
+// Blocks of a streaming kernel, hence partials per dot for the single-workgroup control kernels to reduce.
+// Measured end to end on the 100^3 diffusion eigensolve (fp64 leg): 512 -> 2.96, 1024 -> 3.12, 2048 -> 3.05
+// eigenpairs/s (fewer blocks slow the SpMV, more make every control kernel read more partials).
+constexpr int kNBMax = BNX_NBMAX;
 constexpr int kPartSlots = 80; // dots per partial area
 constexpr int kAreas = 10;     // partial areas
 constexpr int kBlock = 256;
@@ -95,7 +98,8 @@ constexpr int kNR = 4;   // dependency slots per row in registers (block solve)
 constexpr int kNRC = 6;  // the same for level-compressed systems
 constexpr int kNRW = 8;  // wide rows (split schedules of factors with many dependencies per row)
 constexpr int kLongSlice = 1 << 30;  // flag in cnt: the rank's slice has rows longer than kNR
-// LDS values per block (rows + imports + the zero slot): 159 KiB of the 160 KiB of a CU.
+// LDS values per block (rows + imports + the zero slot, then the right-hand side of the block's ranks):
+// 159 KiB of the 160 KiB of a CU.  The partition keeps rows + imports + zero slot within half of it.
 constexpr int kLdsCap64 = 20352;
 constexpr int kLdsCap32 = 40704;
 // default LDS values per block of the partition (measured on the 7-point 100^3 grid)
@@ -232,7 +236,11 @@ struct DevBlk {
   const int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
   const int *cnt = nullptr, *ref4 = nullptr;
   const T *diag = nullptr, *val = nullptr, *val4 = nullptr;  // diag holds reciprocals
-  const int *rank = nullptr;  // rank of each row: the prep runs in row order and scatters (compressed systems)
+  // right-hand-side transform of a level-compressed system in rank order (mw slots per rank): slot e of
+  // rank k names the substituted row mjr[e*npad + k] (-1: none) and its weight's index mtr[e*npad + k]
+  // into the system's transform values
+  const int *mjr = nullptr, *mtr = nullptr;
+  int mw = 0;
 };
 
 // b'_i = b_i - sum_t mv[t] b_{mj[t]}, t in [mp[i], mp[i+1])
@@ -245,8 +253,13 @@ struct RhsT {
 template <typename T>
 struct Tri {
   DevBlk<T> blk;
-  void *blk_scratch = nullptr;  // npad values: right-hand side in rank order
-  void *blk_exp = nullptr;      // nexp values: exported rows (polled by the blocks that import them)
+  // Export buffer of the block solves of this precision, two halves of blk_nexp values, and their two
+  // ticket counters.  A launch uses half (seq & 1) and resets the other half to the sentinel (and its
+  // counter to 0) for the next launch of this precision, which always uses that other half.
+  T *blk_exp = nullptr;
+  int blk_nexp = 0;
+  int *blk_cnt = nullptr;
+  long long *blk_seq = nullptr;  // host: block-solve launches of this precision so far
   int n = 0;
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;
@@ -338,6 +351,11 @@ int launch_spmv(const Launch &L, const Mat<T> &A, const T *x, T *y, int ndy, con
 template <typename T, typename Acc>
 int launch_multidot(const Launch &L, int n, int D, const VList<T> &X, const VList<T> &Y, double *part,
                     const int *gate);
+// Dots of A_0 (and A_1 when na = 2) with each of V_0..V_{nv-1}, then A_0^T A_1 when ab = 1; partial order
+// A_0^T V (nv), A_1^T V (nv), A_0^T A_1.  Returns the number of blocks (partials per dot).
+template <typename T, typename Acc>
+int launch_mdot_list(const Launch &L, int n, int na, const T *A0, const T *A1, int nv, const VList<T> &V, int ab,
+                     double *part, const int *gate);
 int grid_for(size_t work, int nbmax);
 template <typename T>
 void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, const VList<T> &R,
@@ -346,6 +364,9 @@ template <typename Tin, typename Tout>
 void launch_cast(hipStream_t st, size_t n, const Tin *in, Tout *out);
 template <typename T>
 void launch_fill(hipStream_t st, size_t n, T *x, T v);
+// Both halves of a block-solve export buffer (2 * nexp_half values) to the sentinel, both ticket counters to 0.
+template <typename T>
+void launch_blk_reset(hipStream_t st, T *xe_pair, int nexp_half, int *cnt_pair);
 // Latency probes (kind 0: LDS hand-over between waves, 1: global flag between workgroups).
 void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, int *err);
 

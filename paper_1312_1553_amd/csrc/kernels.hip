@@ -232,6 +232,74 @@ int launch_multidot(const Launch &L, int n, int D, const VList<T> &X, const VLis
   return nb;
 }
 
+// Dots of one or two vectors A_a (a < NAV) with a list V (nv vectors), and of A_0 with A_1 (ab = 1):
+//   part[a*nv + d] = sum_i A_a[i] V_d[i],   part[NAV*nv] = sum_i A_0[i] A_1[i]
+// Every vector is read once per element (the generic multi-dot reads a vector once per dot it appears in).
+template <typename T, typename Acc, int NAV, int MAXV>
+__global__ __launch_bounds__(kBlock) void k_mdot_list(int n, const T *__restrict__ A0, const T *__restrict__ A1, int nv,
+                                                      VList<T> V, int ab, double *part, const int *gate) {
+  if (gate && *gate) return;
+  constexpr int NA = NAV * MAXV + 1;
+  Acc acc[NA];
+#pragma unroll
+  for (int j = 0; j < NA; j++) acc[j] = Acc(0);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const Acc a0 = (Acc)A0[i];
+    const Acc a1 = NAV > 1 ? (Acc)A1[i] : Acc(0);
+#pragma unroll
+    for (int d = 0; d < MAXV; d++)
+      if (d < nv) {
+        const Acc v = (Acc)V.p[d][i];
+        acc[d] += a0 * v;
+        if (NAV > 1) acc[MAXV * (NAV - 1) + d] += a1 * v;
+      }
+    if (NAV > 1) acc[NAV * MAXV] += a0 * a1;
+  }
+  // slot j < NAV*MAXV holds A_{j / MAXV}^T V_{j % MAXV}; slot NAV*MAXV holds A_0^T A_1
+  auto out_of = [&](int j) {
+    if (j < NAV * MAXV) return (j % MAXV) < nv ? (j / MAXV) * nv + (j % MAXV) : -1;
+    return (NAV > 1 && ab) ? NAV * nv : -1;
+  };
+  __shared__ double red[kBlock / 64][NA];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NA; j++)
+    if (out_of(j) >= 0) {
+      const Acc sum = wave_sum(acc[j]);
+      if (lane == 0) red[w][j] = (double)sum;
+    }
+  __syncthreads();
+  for (int j = threadIdx.x; j < NA; j += kBlock) {
+    const int out = out_of(j);
+    if (out >= 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < kBlock / 64; ww++) sum += red[ww][j];
+      part[(size_t)out * gridDim.x + blockIdx.x] = sum;
+    }
+  }
+}
+
+template <typename T, typename Acc>
+int launch_mdot_list(const Launch &L, int n, int na, const T *A0, const T *A1, int nv, const VList<T> &V, int ab,
+                     double *part, const int *gate) {
+  const int nb = grid_for((size_t)n, L.nb);
+#define BNX_MDL(NAV, MV)                                                                                            \
+  hipLaunchKernelGGL((k_mdot_list<T, Acc, NAV, MV>), dim3(nb), dim3(kBlock), 0, L.st, n, A0, A1, nv, V, ab, part, \
+                     gate)
+  if (na == 1) {
+    if (nv <= 8) BNX_MDL(1, 8);
+    else if (nv <= 24) BNX_MDL(1, 24);
+    else BNX_MDL(1, kMaxQ + kMaxK + 1);
+  } else {
+    if (nv <= 4) BNX_MDL(2, 4);
+    else if (nv <= 12) BNX_MDL(2, 12);
+    else BNX_MDL(2, kMaxQ);
+  }
+#undef BNX_MDL
+  return nb;
+}
+
 // ------------------------------------------------------------------ triangular solves
 // Right-hand side of row i: b_i - sum_t coef[t] * R[t][i]  (the w = g - R a of Alg. 1 fused in).
 template <typename T>
@@ -400,51 +468,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv_sf(int n, const int *__restrict
   }
 }
 
-// First launch of the LDS-staged solve.  part & 1: right-hand side in rank
-// order, bp[k] = b_i - sum_t coef[t] R_t[i] for i = perm[k] (0 on padding ranks);
-// part & 2: sentinel fill of the export buffer xe (every value a block imports
-// is polled there until it leaves the sentinel state) and reset of the ticket
-// counter.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsv_prep(int part, int nexp, int npad, const int *__restrict__ perm,
-                                                      const T *__restrict__ b, int kfuse, VList<T> R,
-                                                      const double *coef, RhsT<T> M, T *bp, T *xe, int *counter,
-                                                      const int *gate) {
-  if (gate && *gate) return;
-  using U = typename Sentinel<T>::U;
-  if (part & 1)
-    for (int k = blockIdx.x * kBlock + threadIdx.x; k < npad; k += gridDim.x * kBlock) {
-      const int i = perm[k];
-      bp[k] = i >= 0 ? rhs_sys(i, b, kfuse, R, coef, M) : T(0);
-    }
-  if (part & 2) {
-    U *xu = reinterpret_cast<U *>(xe);
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nexp; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
-  }
-}
-
-// The same prep in row order for a level-compressed system: its right-hand-side transform reads
-// neighbouring rows, which are close in row order and scattered in rank order; the result is
-// scattered to rank order instead (every rank of such a schedule is a row).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_trsv_prep_rows(int n, int nexp, const int *__restrict__ rank,
-                                                           const T *__restrict__ b, int kfuse, VList<T> R,
-                                                           const double *coef, RhsT<T> M, T *bp, T *xe,
-                                                           int *counter, const int *gate) {
-  if (gate && *gate) return;
-  using U = typename Sentinel<T>::U;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    bp[rank[i]] = rhs_sys(i, b, kfuse, R, coef, M);
-  U *xu = reinterpret_cast<U *>(xe);
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nexp; i += gridDim.x * kBlock) xu[i] = Sentinel<T>::bits;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
-}
-
 template <typename T, int NR>
 struct RowPre {
   int cnt;
-  T d, s;
+  T d;
   int rr[NR];
   T vv[NR];
 };
@@ -453,11 +480,10 @@ struct RowPre {
 // passes a valid rank for lanes without a row), so the compiler can count the
 // loads in flight exactly and wait only for the ones it needs.
 template <typename T, int NR>
-__device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k, RowPre<T, NR> &P) {
+__device__ __forceinline__ void row_fetch(const DevBlk<T> &F, int k, RowPre<T, NR> &P) {
   const int np = F.npad;
   P.cnt = F.cnt[k];
   P.d = F.diag[k];  // reciprocal of the diagonal
-  P.s = bp[k];
 #pragma unroll
   for (int q = 0; q < NR; q++) {
     P.rr[q] = F.ref4[(size_t)q * np + k];
@@ -481,23 +507,98 @@ __device__ __forceinline__ void row_fetch(const DevBlk<T> &F, const T *bp, int k
 // Every dependency of a row has a lower rank or is an import, so the lowest
 // unfinished row can always proceed.  Waits are bounded: on overflow the value
 // becomes NaN and *err is set.
+// The launch also does what a separate preparation pass would: it gathers the
+// right-hand side of its rows into LDS (b_i minus the fused first loop of Alg. 1,
+// sum_t coef[t] R_t[i], then the transform M of a level-compressed system), and
+// it resets the other half of the export buffer and its ticket counter for the
+// next launch of this precision (also when the launch is gated off).
 template <typename T, int CAP, bool LONG, int NR>
-__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ bp, T *x, T *xe, int *counter,
-                                                    int *err, const int *gate) {
-  if (gate && *gate) return;
+__global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restrict__ b, int kfuse, VList<T> R,
+                                                    const double *coef, RhsT<T> M, T *x, T *xe_pair, int nexp_half,
+                                                    int par, int *cnt_pair, int *err, const int *gate) {
   using U = typename Sentinel<T>::U;
+  {
+    U *xo = reinterpret_cast<U *>(xe_pair) + (size_t)(1 - par) * nexp_half;
+    for (int i = blockIdx.x * 1024 + threadIdx.x; i < nexp_half; i += gridDim.x * 1024) xo[i] = Sentinel<T>::bits;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt_pair[1 - par] = 0;
+  }
+  if (gate && *gate) return;
+  T *xe = xe_pair + (size_t)par * nexp_half;
   constexpr int WC = BNX_TRSV_WC, WI = BNX_TRSV_WI;
   constexpr int WP = 16 - WC - WI;
   static_assert(WP >= 1 && WI >= 1, "wave roles");
   __shared__ U xs[CAP];
   __shared__ int blk_s;
-  if (threadIdx.x == 0) blk_s = atomicAdd(counter, 1);
+  if (threadIdx.x == 0) blk_s = atomicAdd(cnt_pair + par, 1);
   __syncthreads();
   const int blk = blk_s;
   if (blk >= F.nblocks) return;
   const int k0 = F.bptr[blk], nrow = F.brows[blk];
   const int i0 = F.iptr[blk], nimp = F.iptr[blk + 1] - i0;
+  // LDS: rows [0, nrow), imports [nrow, nrow + nimp), the zero slot, then the right-hand side of the rows
+  const int rb = nrow + nimp + 1;
   for (int i = threadIdx.x; i <= nrow + nimp; i += 1024) xs[i] = i < nrow + nimp ? Sentinel<T>::bits : U(0);
+  // right-hand side of the block's ranks (0 for a virtual row), PU ranks per thread whose loads are
+  // in flight together: the row and transform indices first, then every value they name
+  constexpr int PU = 4;
+  for (int t0 = threadIdx.x; t0 < nrow; t0 += PU * 1024) {
+    int ii[PU], kk[PU];
+    T v[PU];
+#pragma unroll
+    for (int u = 0; u < PU; u++) {
+      const int t = t0 + u * 1024;
+      kk[u] = k0 + (t < nrow ? t : 0);
+      ii[u] = t < nrow ? F.perm[kk[u]] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; u++) v[u] = ii[u] >= 0 ? b[ii[u]] : T(0);
+    for (int q = 0; q < kfuse; q++) {  // w = g - R a (first loop of Alg. 1)
+      const T cq = (T)coef[q];
+      const T *Rq = R.p[q];
+#pragma unroll
+      for (int u = 0; u < PU; u++)
+        if (ii[u] >= 0) v[u] -= cq * Rq[ii[u]];
+    }
+    // transform of a level-compressed system, EU slots at a time: the slot indices are rank-indexed and
+    // load beside the row ids (a virtual or padding rank names no row: -1), then every value they name
+    constexpr int EU = 4;
+    for (int e0 = 0; e0 < F.mw; e0 += EU) {
+      int jj[EU][PU], ww[EU][PU];
+      T rj[EU][PU];
+#pragma unroll
+      for (int ee = 0; ee < EU; ee++)
+#pragma unroll
+        for (int u = 0; u < PU; u++) {
+          const bool in = e0 + ee < F.mw;
+          const size_t at = (size_t)(in ? e0 + ee : 0) * F.npad + kk[u];
+          jj[ee][u] = in ? F.mjr[at] : -1;
+          ww[ee][u] = in ? F.mtr[at] : 0;
+        }
+#pragma unroll
+      for (int ee = 0; ee < EU; ee++)
+#pragma unroll
+        for (int u = 0; u < PU; u++) rj[ee][u] = jj[ee][u] >= 0 ? b[jj[ee][u]] : T(0);
+      for (int q = 0; q < kfuse; q++) {
+        const T cq = (T)coef[q];
+        const T *Rq = R.p[q];
+#pragma unroll
+        for (int ee = 0; ee < EU; ee++)
+#pragma unroll
+          for (int u = 0; u < PU; u++)
+            if (jj[ee][u] >= 0) rj[ee][u] -= cq * Rq[jj[ee][u]];
+      }
+#pragma unroll
+      for (int ee = 0; ee < EU; ee++)
+#pragma unroll
+        for (int u = 0; u < PU; u++)
+          if (jj[ee][u] >= 0) v[u] -= M.mv[ww[ee][u]] * rj[ee][u];
+    }
+#pragma unroll
+    for (int u = 0; u < PU; u++) {
+      const int t = t0 + u * 1024;
+      if (t < nrow) xs[rb + t] = to_bits<T>(v[u]);
+    }
+  }
   __syncthreads();
   U *xeu = reinterpret_cast<U *>(xe);
   const int nsl = (nrow + 63) >> 6;
@@ -591,7 +692,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   // the loads in flight)
   auto fetch = [&](int sl, RowPre<T, NR> &P) {
     const int t = (sl << 6) + lane;
-    row_fetch<T, NR>(F, bp, (sl < nsl && t < nrow) ? k0 + t : k0, P);
+    row_fetch<T, NR>(F, (sl < nsl && t < nrow) ? k0 + t : k0, P);
   };
   // The polling loop runs until no lane of the wave is pending (a ballot), so a
   // row's store sits inside the iteration in which it finishes: code after a
@@ -600,6 +701,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   auto solve_slice = [&](const RowPre<T, NR> &cur, int sl) {
     const int t = (sl << 6) + lane;
     bool fin = t >= nrow;
+    const T s0 = fin ? T(0) : from_bits<T>(xs[rb + t]);
     const int gsl = (k0 >> 6) + sl;
     // lane 0 always holds a row of the slice; its flag tells whether any row is long (schedules
     // without long rows run the instantiation that has no general path)
@@ -618,7 +720,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
 #pragma unroll
           for (int q = 0; q < NR; q++) ok = ok && u[q] != Sentinel<T>::bits;
           if (ok) {
-            T acc = cur.s;
+            T acc = s0;
 #pragma unroll
             for (int q = 0; q < NR; q++) acc -= cur.vv[q] * from_bits<T>(u[q]);
             __hip_atomic_store(&xs[t], to_bits<T>(acc * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -660,7 +762,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     };
     if (!fin && nlong > NR) load_chunk();  // in flight while the first NR are polled
     bool head = false;                     // the first NR are consumed
-    T s = cur.s;
+    T s = s0;
     int spins = 0;
     while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
       if (!fin) {
@@ -793,10 +895,11 @@ void launch_probe(hipStream_t st, int kind, int hops, int *flags, int *counter, 
 }
 
 template <typename T, int CAP>
-static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, const int *gate) {
+static void launch_blk(const Launch &L, const Tri<T> &F, const T *b, int kfuse, const VList<T> &R,
+                       const double *coef, T *x, int par, const int *gate) {
 #define BNX_BLK(LONG, NR)                                                                                         \
-  hipLaunchKernelGGL((k_trsv_blk<T, CAP, LONG, NR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, bp, x,    \
-                     reinterpret_cast<T *>(F.blk_exp), L.counter, &L.ctl->err, gate)
+  hipLaunchKernelGGL((k_trsv_blk<T, CAP, LONG, NR>), dim3(F.blk.nblocks), dim3(1024), 0, L.st, F.blk, b, kfuse,  \
+                     R, coef, F.M, x, F.blk_exp, F.blk_nexp, par, F.blk_cnt, &L.ctl->err, gate)
   // three-slot schedules (no row longer than three), level-compressed systems (kNRC slots)
   // and wide split schedules (kNRW slots, float only: eight double slots spill registers)
   // have no row beyond their slots and need no general path
@@ -815,23 +918,23 @@ static void launch_blk(const Launch &L, const Tri<T> &F, const T *bp, T *x, cons
 }
 
 template <typename T>
+void launch_blk_reset(hipStream_t st, T *xe_pair, int nexp_half, int *cnt_pair) {
+  const size_t m = 2 * (size_t)nexp_half;
+  hipLaunchKernelGGL((k_sentinel<T>), dim3(grid_for(m > 0 ? m : 1, 1024)), dim3(kBlock), 0, st, m, xe_pair, cnt_pair,
+                     nullptr);
+  hipLaunchKernelGGL((k_sentinel<T>), dim3(1), dim3(kBlock), 0, st, (size_t)0, xe_pair, cnt_pair + 1, nullptr);
+}
+
+template <typename T>
 void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, const VList<T> &R,
                  const double *coef, const int *gate) {
   if (L.trsv_mode == 0 && F.blk.nblocks > 0) {
     const bool prof0 = L.prof && L.prof->on;
     hipEvent_t ev0 = nullptr;
-    T *bp = reinterpret_cast<T *>(F.blk_scratch);
-    const int nb = grid_for((size_t)F.blk.npad, kNBMax);
-    if (F.blk.rank)
-      hipLaunchKernelGGL((k_trsv_prep_rows<T>), dim3(grid_for((size_t)F.n, kNBMax)), dim3(kBlock), 0, L.st, F.n,
-                         F.blk.nexp, F.blk.rank, b, kfuse, R, coef, F.M, bp, reinterpret_cast<T *>(F.blk_exp),
-                         L.counter, gate);
-    else
-      hipLaunchKernelGGL((k_trsv_prep<T>), dim3(nb), dim3(kBlock), 0, L.st, 3, F.blk.nexp, F.blk.npad, F.blk.perm,
-                         b, kfuse, R, coef, F.M, bp, reinterpret_cast<T *>(F.blk_exp), L.counter, gate);
+    const int par = (int)((*F.blk_seq)++ & 1);
     if (prof0) L.prof->begin(L.st, &ev0);
-    if constexpr (sizeof(T) == 8) launch_blk<T, kLdsCap64>(L, F, bp, x, gate);
-    else launch_blk<T, kLdsCap32>(L, F, bp, x, gate);
+    if constexpr (sizeof(T) == 8) launch_blk<T, kLdsCap64>(L, F, b, kfuse, R, coef, x, par, gate);
+    else launch_blk<T, kLdsCap32>(L, F, b, kfuse, R, coef, x, par, gate);
     if (prof0) L.prof->end(L.st, (F.lower ? 2 : 4) + (sizeof(T) == 8 ? 0 : 1), ev0);
     return;
   }
@@ -902,9 +1005,12 @@ void launch_fill(hipStream_t st, size_t n, T *x, T v) {
                               const VList<T> &, double *, const int *);                                              \
   template int launch_multidot<T, T>(const Launch &, int, int, const VList<T> &, const VList<T> &, double *,          \
                                      const int *);                                                                   \
+  template int launch_mdot_list<T, T>(const Launch &, int, int, const T *, const T *, int, const VList<T> &, int,      \
+                                      double *, const int *);                                                        \
   template void launch_trsv<T>(const Launch &, const Tri<T> &, const T *, T *, int, const VList<T> &, const double *, \
                                const int *);                                                                         \
-  template void launch_fill<T>(hipStream_t, size_t, T *, T);
+  template void launch_fill<T>(hipStream_t, size_t, T *, T);                                                \
+  template void launch_blk_reset<T>(hipStream_t, T *, int, int *);
 INST(double)
 INST(float)
 template int launch_multidot<float, double>(const Launch &, int, int, const VList<float> &, const VList<float> &,

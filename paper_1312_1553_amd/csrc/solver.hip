@@ -121,12 +121,15 @@ __device__ void first_loop(DevCtl *c) {
 template <typename T, int MAXD>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(int n, const DevCtl *c, double sgn, const T *r, int m, VList<T> Q,
                                                      int k, VList<T> S, T *g, T *s, T *t, double *part) {
+  __shared__ T qr[kMaxQ];  // coefficients read once per workgroup
+  for (int q = threadIdx.x; q < m; q += kBlock) qr[q] = (T)c->Qr[q];
+  __syncthreads();
   T acc[MAXD];
 #pragma unroll
   for (int d = 0; d < MAXD; d++) acc[d] = T(0);
   GRIDLOOP(i, n) {
     T v = r[i];
-    for (int q = 0; q < m; q++) v -= (T)c->Qr[q] * Q.p[q][i];
+    for (int q = 0; q < m; q++) v -= qr[q] * Q.p[q][i];
     v *= (T)sgn;
     g[i] = v;
     s[i] = T(0);
@@ -150,13 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, const DevCtl *c, c
   if (c->done) return;
   const T theta = (T)c->theta, gamma = (T)c->gamma;
   const int eig = c->eigtest;
+  __shared__ T zy[kMaxQ];  // coefficients read once per workgroup
+  for (int q = threadIdx.x; q < m; q += kBlock) zy[q] = (T)c->zy[q];
+  __syncthreads();
   T acc[MAXD];
 #pragma unroll
   for (int d = 0; d < MAXD; d++) acc[d] = T(0);
   GRIDLOOP(i, n) {
     const T api = ap[i], pi = p[i];
     T y = api - theta * pi;
-    for (int q = 0; q < m; q++) y -= (T)c->zy[q] * Q.p[q][i];
+    for (int q = 0; q < m; q++) y -= zy[q] * Q.p[q][i];
     const T si = s[i] + gamma * pi;
     const T gi = g[i] - gamma * y;
     s[i] = si;
@@ -200,14 +206,18 @@ __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, con
                                                      double *part) {
   if (c->done) return;
   const T beta = (T)c->beta;
+  __shared__ T es[kMaxK], zq[kMaxQ];  // coefficients read once per workgroup
+  for (int t = threadIdx.x; t < k; t += kBlock) es[t] = (T)c->e[t];
+  for (int q = threadIdx.x; q < m; q += kBlock) zq[q] = (T)c->zQ[q];
+  __syncthreads();
   constexpr int NA = MAXD > 0 ? MAXD : 1;
   T acc[NA];
 #pragma unroll
   for (int d = 0; d < NA; d++) acc[d] = T(0);
   GRIDLOOP(i, n) {
     T v = c0[i];
-    for (int s = 0; s < k; s++) v -= (T)c->e[s] * S.p[s][i];
-    for (int q = 0; q < m; q++) v -= (T)c->zQ[q] * Q.p[q][i];
+    for (int s = 0; s < k; s++) v -= es[s] * S.p[s][i];
+    for (int q = 0; q < m; q++) v -= zq[q] * Q.p[q][i];
     if (with_beta) v += beta * p[i];
     p[i] = v;
 #pragma unroll
@@ -372,13 +382,17 @@ __global__ __launch_bounds__(kBlock) void k_comb(int n, T *out, const T *b0, dou
   if (gate && *gate) return;
   const T c0 = (T)(cb0c * (cb0d ? *cb0d : 1.0));
   const T c1 = cb1 ? (T)(*cb1) : T(0);
+  // the coefficients, read once per workgroup (the stores to out could alias them)
+  __shared__ T lc[kMaxVec];
+  for (int t = threadIdx.x; t < nt; t += kBlock) lc[t] = (T)(sgn * coef[t]);
+  __syncthreads();
   T acc[MAXD > 0 ? MAXD : 1];
 #pragma unroll
   for (int d = 0; d < (MAXD > 0 ? MAXD : 1); d++) acc[d] = T(0);
   GRIDLOOP(i, n) {
     T v = b0 ? c0 * b0[i] : T(0);
     if (b1) v += c1 * b1[i];
-    for (int t = 0; t < nt; t++) v += (T)(sgn * coef[t]) * V.p[t][i];
+    for (int t = 0; t < nt; t++) v += lc[t] * V.p[t][i];
     out[i] = v;
 #pragma unroll
     for (int d = 0; d < MAXD; d++)
@@ -980,7 +994,7 @@ struct bnx_ctx {
     int *eptr = nullptr, *erank = nullptr, *orow = nullptr, *oslot = nullptr;
     int *perm = nullptr, *slice_ptr = nullptr, *slice_nnz = nullptr, *ref = nullptr;
     int *valmap = nullptr, *diagmap = nullptr, *cnt = nullptr, *ref4 = nullptr, *valmap4 = nullptr;
-    int *rank = nullptr;  // rank of each row, for the row-order prep of a level-compressed schedule
+    int *mjr = nullptr, *mtr = nullptr, mw = 0;  // rank-order right-hand-side transform (compressed systems)
     double *diag64 = nullptr, *val64 = nullptr, *val4_64 = nullptr;
     float *diag32 = nullptr, *val32 = nullptr, *val4_32 = nullptr;
   } blk[2][2];  // [direction][0 = fp64 LDS capacity, 1 = fp32 LDS capacity]
@@ -997,8 +1011,14 @@ struct bnx_ctx {
     double *v = nullptr, *mv = nullptr;
     float *v32 = nullptr, *mv32 = nullptr;
   } sys[2];
-  double *blk_rhs = nullptr;  // right-hand side of a block solve in rank order (largest npad)
-  double *blk_exp = nullptr;  // export buffer of a block solve (largest nexp)
+  // export buffers of the block solves, per precision two halves of the largest nexp of its two
+  // schedules, and their ticket counters ([0..1] fp64, [2..3] fp32); a launch uses one half and resets
+  // the other for the next launch of the same precision (blk_seq counts them)
+  double *blk_exp64 = nullptr;
+  float *blk_exp32 = nullptr;
+  int blk_nexp64 = 0, blk_nexp32 = 0;
+  int *blk_cnt = nullptr;
+  mutable long long blk_seq[2] = {0, 0};
   int *probe_flags = nullptr;  // latency probe flags (allocated on first use)
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
@@ -1129,8 +1149,10 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
     F.blk.ref4 = b.ref4;
     F.blk.val4 = b.val4_64;
   }
-  F.blk_scratch = blk_rhs;
-  F.blk_exp = blk_exp;
+  F.blk_exp = blk_exp64;
+  F.blk_nexp = blk_nexp64;
+  F.blk_cnt = blk_cnt;
+  F.blk_seq = &blk_seq[0];
   F.n = n;
   F.lower = lower;
   F.rp = lower ? Lrp : Ltrp;
@@ -1172,10 +1194,14 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
     F.blk.cnt = b.cnt;
     F.blk.ref4 = b.ref4;
     F.blk.val4 = b.val4_32;
-    F.blk.rank = b.rank;
+    F.blk.mjr = b.mjr;
+    F.blk.mtr = b.mtr;
+    F.blk.mw = b.mw;
   }
-  F.blk_scratch = blk_rhs;
-  F.blk_exp = blk_exp;
+  F.blk_exp = blk_exp32;
+  F.blk_nexp = blk_nexp32;
+  F.blk_cnt = blk_cnt ? blk_cnt + 2 : nullptr;
+  F.blk_seq = &blk_seq[1];
   F.n = n;
   F.lower = lower;
   if (lps) {
@@ -1343,17 +1369,10 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
   VList<T> ly{}, lx{};
   ly.p[0] = w.p;
   lx.p[0] = w.p;
-  VList<T> mdX{}, mdY{};
-  for (int s = 0; s < k; s++) {
-    mdX.p[s] = R.p[s];
-    mdY.p[s] = w.c0;
-  }
-  for (int q = 0; q < m; q++) {
-    mdX.p[k + q] = Q.p[q];
-    mdY.p[k + q] = w.c0;
-  }
+  VList<T> mdX{};  // c0 against R (k), Q (m), g
+  for (int s = 0; s < k; s++) mdX.p[s] = R.p[s];
+  for (int q = 0; q < m; q++) mdX.p[k + q] = Q.p[q];
   mdX.p[k + m] = w.g;
-  mdY.p[k + m] = w.c0;
   const int Du = 3 + k + m;
 
   Poll poll(C);
@@ -1362,7 +1381,7 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     // c0 = P0^ (g - R a)   (first loop fused into the forward solve)
     launch_trsv<T>(L, Lf, w.g, w.z, k, R, c->a, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, R, nullptr, gate);
-    int nbd = launch_multidot<T, T>(L, n, k + m + 1, mdX, mdY, area(L, 3), gate);
+    int nbd = launch_mdot_list<T, T>(L, n, 1, w.c0, nullptr, k + m + 1, mdX, 0, area(L, 3), gate);
     hipLaunchKernelGGL(c_pcg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd);
     if (2 * m <= 8)
       hipLaunchKernelGGL((k_pcg_newp<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.c0, k, S, m, Q, w.p,
@@ -1456,15 +1475,6 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   // Ax
   launch_spmv<T>(L, A, w.x, w.Ax, 0, VList<T>{}, 0, VList<T>{}, nullptr, nullptr);
   (*mvp)++;
-  VList<T> mdX{}, mdY{};  // one pass after the solves: Qt^T g, Qt^T c0, g^T c0
-  for (int q = 0; q < nq; q++) {
-    mdX.p[q] = Qt.p[q];
-    mdY.p[q] = w.dg;
-    mdX.p[nq + q] = Qt.p[q];
-    mdY.p[nq + q] = w.c0;
-  }
-  mdX.p[2 * nq] = w.dg;
-  mdY.p[2 * nq] = w.c0;
   VList<T> ly{}, lx{};
   ly.p[0] = w.d;
   lx.p[0] = w.Ax;
@@ -1481,7 +1491,8 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
-    int nbd = launch_multidot<T, T>(L, n, 2 * nq + 1, mdX, mdY, area(L, 3), gate);
+    // one pass after the solves: Qt^T g, Qt^T c0, g^T c0
+    int nbd = launch_mdot_list<T, T>(L, n, 2, w.dg, w.c0, nq, Qt, 1, area(L, 3), gate);
     hipLaunchKernelGGL(c_dacg_beta, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 3), nbd, nq);
     // d = -(c0 - Qt zQ) + beta d
     // (dots of the new d with Ax, x and d itself)
@@ -2245,15 +2256,19 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     for (int pr = 0; pr < 2; pr++) {
       auto &b = C->blk[dir][pr];
       for (int *q : {b.bptr, b.brows, b.iptr, b.isrc, b.eptr, b.erank, b.orow, b.oslot, b.perm, b.slice_ptr,
-                     b.slice_nnz, b.ref, b.valmap, b.diagmap, b.cnt, b.ref4, b.valmap4, b.rank})
+                     b.slice_nnz, b.ref, b.valmap, b.diagmap, b.cnt, b.ref4, b.valmap4, b.mjr, b.mtr})
         C->release(q);
       for (double *q : {b.diag64, b.val64, b.val4_64}) C->release(q);
       for (float *q : {b.diag32, b.val32, b.val4_32}) C->release(q);
       b = bnx_ctx::BlkDev{};
     }
   for (int *q : {C->Lrp, C->Lci, C->mapL, C->Ltrp, C->Ltci, C->mapLt, C->levL, C->levLt}) C->release(q);
-  for (double *q : {C->Lv, C->Ltv, C->blk_rhs, C->blk_exp}) C->release(q);
-  for (float *q : {C->Lv32, C->Ltv32}) C->release(q);
+  for (double *q : {C->Lv, C->Ltv, C->blk_exp64}) C->release(q);
+  for (float *q : {C->Lv32, C->Ltv32, C->blk_exp32}) C->release(q);
+  C->release(C->blk_cnt);
+  C->blk_exp64 = nullptr;
+  C->blk_exp32 = nullptr;
+  C->blk_cnt = nullptr;
   for (auto &S : C->sys) {
     for (int *q : {S.rp, S.ci, S.lev, S.direct, S.tp, S.ta, S.tb, S.tc, S.mp, S.mj, S.ma, S.mc}) C->release(q);
     for (double *q : {S.v, S.mv}) C->release(q);
@@ -2296,8 +2311,8 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   // values finish_factor derives from the factor's.
   bool lps = true;
   if (const char *e = getenv("BNX_LPS")) lps = atoi(e) != 0;  // tuning override
+  SolveSys Sf, Sb;  // host copies, kept for the rank-order transforms of the block schedules
   {
-    SolveSys Sf, Sb;
     C->lps = lps && compress_both(a, split, Sf, Sb);
     if (C->lps) {
       Analysis &S = C->anS;
@@ -2359,12 +2374,17 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     int cap = pr == 0 ? kBlkTarget64 : (cmp ? kBlkTarget32C : kBlkTarget32);
     if (const char *e = getenv(pr == 0 ? "BNX_BLK_CAP64" : "BNX_BLK_CAP32"))  // tuning override
       cap = atoi(e);
-    cap = std::max(256, std::min(cap, pr == 0 ? kLdsCap64 : kLdsCap32));
+    // the block's right-hand side takes as many LDS values as its ranks: half the LDS for the rest
+    const int lds = pr == 0 ? kLdsCap64 : kLdsCap32;
+    cap = std::max(256, std::min(cap, lds / 2 - 128));  // 128: padding of a block to whole slices
     if (!partition_rows(sa, cap, prow, pstart, split, nr, cmp ? &a : nullptr)) continue;  // no block schedule
     for (int dir = 0; dir < 2; dir++) {
       BlockSched bs;
       block_schedule(sa, dir == 0, prow, pstart, bs, split, nr);
-      if (bs.max_lds > (pr == 0 ? kLdsCap64 : kLdsCap32)) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
+      int need = 0;  // rows + imports + zero slot + right-hand side of the rows
+      for (int q = 0; q < bs.nblocks; q++)
+        need = std::max(need, 2 * bs.brows[q] + (bs.iptr[q + 1] - bs.iptr[q]) + 1);
+      if (bs.max_lds > lds || need > lds) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
       auto &b = C->blk[dir][pr];
       b.n = bs.n;
       b.nr = bs.nr;
@@ -2395,16 +2415,22 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
       b.cnt = up(bs.cnt);
       b.ref4 = up(bs.ref4);
       b.valmap4 = up(bs.valmap4);
-      // row-order prep for the compressed systems (their right-hand-side transform reads
-      // neighbouring rows): every rank of a block must be a row (no virtual rows), so that
-      // scattering the rows covers every rank the solve reads
-      bool rows_only = cmp;
-      for (int q = 0; q < bs.nblocks && rows_only; q++) rows_only = bs.nreal[q] == bs.brows[q];
-      if (rows_only) {
-        std::vector<int> rk(bs.n, 0);
-        for (int k = 0; k < bs.npad; k++)
-          if (bs.perm[k] >= 0) rk[bs.perm[k]] = k;
-        b.rank = up(rk);
+      if (cmp) {  // the compressed system's right-hand-side transform, in rank order
+        const SolveSys &Q = dir == 0 ? Sf : Sb;
+        int mw = 0;
+        for (int i = 0; i < n; i++) mw = std::max(mw, Q.mp[i + 1] - Q.mp[i]);
+        std::vector<int> mjr((size_t)mw * bs.npad, -1), mtr((size_t)mw * bs.npad, 0);
+        for (int k = 0; k < bs.npad; k++) {
+          const int i = bs.perm[k];
+          if (i < 0) continue;
+          for (int t = Q.mp[i]; t < Q.mp[i + 1]; t++) {
+            mjr[(size_t)(t - Q.mp[i]) * bs.npad + k] = Q.mj[t];
+            mtr[(size_t)(t - Q.mp[i]) * bs.npad + k] = t;
+          }
+        }
+        b.mw = mw;
+        b.mjr = up(mjr);
+        b.mtr = up(mtr);
       }
       const size_t np = (size_t)bs.npad;
       if (pr == 0) {
@@ -2420,14 +2446,14 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     }
   }
   {
-    int np = n;
-    for (int dir = 0; dir < 2; dir++)
-      for (int pr = 0; pr < 2; pr++) np = std::max(np, C->blk[dir][pr].npad);
-    C->blk_rhs = C->alloc<double>(np);
-    int ne = 1;
-    for (int dir = 0; dir < 2; dir++)
-      for (int pr = 0; pr < 2; pr++) ne = std::max(ne, C->blk[dir][pr].nexp);
-    C->blk_exp = C->alloc<double>(ne);
+    C->blk_nexp64 = std::max({1, C->blk[0][0].nexp, C->blk[1][0].nexp});
+    C->blk_nexp32 = std::max({1, C->blk[0][1].nexp, C->blk[1][1].nexp});
+    C->blk_exp64 = C->alloc<double>(2 * (size_t)C->blk_nexp64);
+    C->blk_exp32 = C->alloc<float>(2 * (size_t)C->blk_nexp32);
+    C->blk_cnt = C->alloc<int>(4);
+    launch_blk_reset<double>(C->st, C->blk_exp64, C->blk_nexp64, C->blk_cnt);
+    launch_blk_reset<float>(C->st, C->blk_exp32, C->blk_nexp32, C->blk_cnt + 2);
+    C->blk_seq[0] = C->blk_seq[1] = 0;
   }
   C->sync();
   C->ta = &a;
