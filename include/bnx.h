@@ -235,6 +235,21 @@ bnx_status bnx_spmv(bnx_ctx *ctx, int precision, const double *x, double *y);
 bnx_status bnx_ic_apply(bnx_ctx *ctx, int precision, int which, const double *b, double *x);
 
 /*
+ * bnx_ic_apply without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and results as bnx_ic_apply.
+ * The temporaries bnx_ic_apply allocates per call (one n-vector of doubles,
+ * or three of floats in BNX_MIXED) live instead in a 12 MiB device array of
+ * the library, one copy per device for the life of the process, so
+ * n <= 1048576 (larger n: BNX_E_ARG, use bnx_ic_apply).  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (different streams or threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero.
+ * Errors: as bnx_ic_apply, and BNX_E_ARG when n is too large.
+ */
+bnx_status bnx_ic_apply_noalloc(bnx_ctx *ctx, int precision, int which, const double *b, double *x);
+
+/*
  * Alg. 1: c = P_k g.  S, R: n x k (column t = pair t, oldest first);
  * alpha_t = s_t^T r_t is formed in double.  Q: n x m projection block (m >= 0,
  * orthonormal columns).  g should be orthogonal to Q (the algorithm omits the

@@ -59,7 +59,7 @@ class Stats(C.Structure):
 
 EXPORTS = ["bnx_default_solve_opts", "bnx_default_factor_opts", "bnx_create_csr", "bnx_set_values", "bnx_factor",
            "bnx_solve", "bnx_backward", "bnx_set_adjoint_params", "bnx_last_error", "bnx_destroy", "bnx_spmv",
-           "bnx_ic_apply", "bnx_prec_apply", "bnx_correction_solve", "bnx_dacg", "bnx_set_trsv_mode",
+           "bnx_ic_apply", "bnx_ic_apply_noalloc", "bnx_prec_apply", "bnx_correction_solve", "bnx_dacg", "bnx_set_trsv_mode",
            "bnx_set_profiling", "bnx_kernel_time", "bnx_probe_latency", "bnx_factor_info"]
 
 _lib = None
@@ -91,6 +91,7 @@ def load(path: str = LIBPATH):
     L.bnx_destroy.restype = None
     L.bnx_spmv.argtypes = [_vp, C.c_int, _vp, _vp]
     L.bnx_ic_apply.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp]
+    L.bnx_ic_apply_noalloc.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp]
     L.bnx_prec_apply.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp, _vp, _vp]
     L.bnx_correction_solve.argtypes = [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, _vp, C.c_double, C.c_int, C.c_double,
                                        C.c_int, C.c_double, _vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -182,6 +183,10 @@ def bnx_spmv(h, precision, x, y):
 
 def bnx_ic_apply(h, precision, which, b, x):
     return _check(h, load().bnx_ic_apply(h, precision, which, _ptr(b), _ptr(x)))
+
+
+def bnx_ic_apply_noalloc(h, precision, which, b, x):
+    return _check(h, load().bnx_ic_apply_noalloc(h, precision, which, _ptr(b), _ptr(x)))
 
 
 def bnx_prec_apply(h, precision, k, S, R, m, Q, g, c):

@@ -264,7 +264,7 @@ struct Tri {
   const int *rp = nullptr, *ci = nullptr;
   const T *v = nullptr;
   const int *lev_rows = nullptr;
-  std::vector<int> lev_ptr;  // host copy for level launches
+  const std::vector<int> *lev_ptr = nullptr;  // level boundaries for level launches (host, owned by the context)
   int nlev = 0;
   int max_rows = 0;          // largest level
   bool lower = true;         // true: diag last (L); false: diag first (L^T)

@@ -944,7 +944,7 @@ void launch_trsv(const Launch &L, const Tri<T> &F, const T *b, T *x, int kfuse, 
   if (L.trsv_mode == 1) {  // one launch per dependency level
     if (prof) L.prof->begin(L.st, &ev);
     for (int l = 0; l < F.nlev; l++) {
-      int r0 = F.lev_ptr[l], r1 = F.lev_ptr[l + 1];
+      int r0 = (*F.lev_ptr)[l], r1 = (*F.lev_ptr)[l + 1];
       int nb = (r1 - r0 + kBlock - 1) / kBlock;
       if (F.lower)
         hipLaunchKernelGGL((k_trsv_level<T, true>), dim3(nb), dim3(kBlock), 0, L.st, r0, r1, F.lev_rows, F.rp, F.ci,
@@ -1015,6 +1015,7 @@ INST(double)
 INST(float)
 template int launch_multidot<float, double>(const Launch &, int, int, const VList<float> &, const VList<float> &,
                                             double *, const int *);
+template void launch_fill<int>(hipStream_t, size_t, int *, int);
 template void launch_cast<double, float>(hipStream_t, size_t, const double *, float *);
 template void launch_cast<float, double>(hipStream_t, size_t, const float *, double *);
 template void launch_cast<double, double>(hipStream_t, size_t, const double *, double *);

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -1020,6 +1021,7 @@ struct bnx_ctx {
   int *blk_cnt = nullptr;
   mutable long long blk_seq[2] = {0, 0};
   int *probe_flags = nullptr;  // latency probe flags (allocated on first use)
+  void *scratch = nullptr;     // device address of this device's copy of the no-allocation scratch array
   DevCtl *ctl = nullptr;
   DevCtl *hctl = nullptr;  // pinned readback
   double *part = nullptr;
@@ -1161,7 +1163,7 @@ Tri<double> bnx_ctx::tri<double>(bool lower) const {
   F.lev_rows = lower ? levL : levLt;
   const Analysis &la = *ta;
   const Levels &lv = lower ? la.levL : la.levLt;
-  F.lev_ptr = lv.ptr;
+  F.lev_ptr = &lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
   return F;
@@ -1221,7 +1223,7 @@ Tri<float> bnx_ctx::tri<float>(bool lower) const {
   }
   const Analysis &la = lps ? anS : *ta;
   const Levels &lv = lower ? la.levL : la.levLt;
-  F.lev_ptr = lv.ptr;
+  F.lev_ptr = &lv.ptr;
   F.nlev = lv.nlev;
   F.max_rows = lv.max_rows;
   return F;
@@ -2604,12 +2606,43 @@ bool prec_ok(int p) { return p == BNX_FP64 || p == BNX_MIXED; }
 
 }  // namespace
 
+// ================================================================== no-allocation scratch
+// Scratch of bnx_ic_apply_noalloc: the temporaries that bnx_ic_apply allocates per call (one n-vector
+// of doubles, or three n-vectors of floats), for n <= kNoAllocMaxN.  Each device holds its own copy
+// for the life of the process.  Host code never uses the array's name as an address: the device
+// address of each device's copy is taken once, with hipGetSymbolAddress, when the first context is
+// created on that device, and kept per device.
+constexpr int kNoAllocMaxN = 1 << 20;
+static __device__ __align__(256) double scratch[(size_t)kNoAllocMaxN * 3 / 2];  // 12 MiB
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// the current device's scratch address (the device of the context being created)
+void *scratch_address() {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw ApiError{BNX_E_ARG, "device ordinal out of range for the scratch table"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) throw HipError{std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
+}  // namespace
+
 // ================================================================== C-ABI
 namespace {
 template <typename T>
-static void ic_apply_t(bnx_ctx *C, int which, const T *b, T *x, T *tmp) {
-  const Launch L = C->launch();
-  HIPCHK(hipMemsetAsync(&C->ctl->err, 0, sizeof(int), C->st));
+static void ic_apply_t(bnx_ctx *C, int which, const T *b, T *x, T *tmp, bool events = true) {
+  Launch L = C->launch();
+  if (!events) L.prof = nullptr;  // the event timing creates events; the no-allocation path records none
+  launch_fill<int>(C->st, 1, &C->ctl->err, 0);
   if (which == 0) launch_trsv<T>(L, C->tri<T>(true), b, x, 0, VList<T>{}, nullptr, nullptr);
   else if (which == 1) launch_trsv<T>(L, C->tri<T>(false), b, x, 0, VList<T>{}, nullptr, nullptr);
   else {
@@ -2801,6 +2834,7 @@ bnx_status bnx_create_csr(bnx_ctx **out, int64_t n, int64_t nnz, const int32_t *
   C->device_ptrs = device_ptrs ? 1 : 0;
   C->st = (hipStream_t)hip_stream;
   bnx_status s = guarded(C, [&]() -> bnx_status {
+    C->scratch = scratch_address();
     C->an.n = C->n;
     C->an.nnz = C->nnz;
     C->an.rp.resize(n + 1);
@@ -3077,6 +3111,28 @@ bnx_status bnx_ic_apply(bnx_ctx *C, int precision, int which, const double *b, d
       C->release(bf);
       C->release(xf);
       C->release(tf);
+    }
+    return BNX_OK;
+  });
+}
+
+bnx_status bnx_ic_apply_noalloc(bnx_ctx *C, int precision, int which, const double *b, double *x) {
+  if (!C || !b || !x || !prec_ok(precision) || which < 0 || which > 2) return BNX_E_ARG;
+  return guarded(C, [&]() -> bnx_status {
+    if (!C->factored) throw ApiError{BNX_E_STATE, "bnx_factor must precede bnx_ic_apply_noalloc"};
+    const int n = C->n;
+    if (n > kNoAllocMaxN)
+      throw ApiError{BNX_E_ARG, "bnx_ic_apply_noalloc: n = " + std::to_string(n) + " exceeds its scratch (n <= " +
+                                    std::to_string(kNoAllocMaxN) + "); use bnx_ic_apply"};
+    if (!C->scratch) throw ApiError{BNX_E_STATE, "no scratch address for this context's device"};
+    if (precision == BNX_FP64) {
+      ic_apply_t<double>(C, which, b, x, static_cast<double *>(C->scratch), false);
+    } else {
+      float *bf = static_cast<float *>(C->scratch), *xf = bf + n, *tf = xf + n;
+      launch_cast<double, float>(C->st, n, b, bf);
+      ic_apply_t<float>(C, which, bf, xf, tf, false);
+      launch_cast<float, double>(C->st, n, xf, x);
+      C->sync();
     }
     return BNX_OK;
   });
