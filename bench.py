@@ -35,21 +35,26 @@ def trsv_bytes(n, nnzL, vb):
     return (vb + 4) * nnzL + 4 * (n + 1) + 2 * vb * n
 
 
-def counter_traffic(kname, n_grid):
+def counter_traffic(kname, n_grid, levels):
     """HBM bytes per launch of the named kernel from the committed rocprofv3 counter summary, or None when the
-    summary is for another workload or the kernel source has changed since the counters were taken."""
+    summary is for another workload or another system (level count), or the kernel source has changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_counters_diffusion3d_100.txt")
     src = os.path.join(ROOT, "paper_1312_1553_amd", "csrc", "kernels.hip")
     if n_grid != 100 or not os.path.exists(path):
         return None
     tag = ("trsv_" if kname.startswith("trsv") else "spmv_") + kname.split("_")[-1]
-    sha, val = None, None
+    sha, val, lev = None, None, None
     for ln in open(path):
         if ln.startswith("kernels.hip sha256:"):
             sha = ln.split(":", 1)[1].strip()
-        elif tag and ln.startswith(f"traffic_bytes {tag}:"):
+        elif ln.startswith(f"traffic_bytes {tag}:"):
             val = int(ln.split(":", 1)[1])
+        elif ln.startswith("levels:"):
+            lev = int(ln.split(":", 1)[1])
     if val is None or sha != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if tag.startswith("trsv") and lev != levels:
         return None
     return val
 
@@ -363,7 +368,7 @@ def main():
                                                        / np.array(fp64["evals"]))),
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": counter_traffic(kname, N) if args.workload == "diffusion100" else None,
+                     "traffic": counter_traffic(kname, N, levels) if args.workload == "diffusion100" else None,
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2),
                      "levels": levels,
                      "limiter": ("latency: a chain of %d dependent levels" % levels) if kname.startswith("trsv")

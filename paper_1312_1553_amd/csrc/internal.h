@@ -106,6 +106,8 @@ constexpr int kLdsCap32 = 40704;
 constexpr int kBlkTarget64 = 7168;
 constexpr int kBlkTarget32 = 12288;
 constexpr int kBlkTarget32C = 8192;  // FP32, level-compressed systems: 256 blocks on the 100^3 grid
+// level-pair substitution is tried for factors whose levels hold fewer rows than this on average
+constexpr double kLpsRowsPerLevel = 512.0;
 
 struct BlockSched {
   int n = 0, npad = 0, nblocks = 0, nslices = 0, ell = 0, nimp = 0;

@@ -2310,9 +2310,15 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
   // Level-pair substitution (compress_both) when it shortens both dependency chains below
   // 3/4 and keeps every row within kNRC dependencies, or, with split schedules, grows the
   // entries by at most half: the fp32 solves then run the two compressed systems, whose
-  // values finish_factor derives from the factor's.
-  bool lps = true;
-  if (const char *e = getenv("BNX_LPS")) lps = atoi(e) != 0;  // tuning override
+  // values finish_factor derives from the factor's.  It is tried only when a level holds
+  // fewer than kLpsRowsPerLevel rows on average: thin levels cost their hand-over latency
+  // and halving them pays (500k-node geometric graph, 176 rows per level: fp32 solve 460
+  // against 545 us), while a compressed level of a wide one carries twice the rows and up
+  // to six dependencies per row, costs about twice as much, and the right-hand-side
+  // transform adds gathers to every solve (100^3 grid, 3356 rows per level: 108 against
+  // 103 us in the eigensolve, 3.26 against 3.47 eigenpairs/s mixed).
+  bool lps = (double)n / std::max(1, a.levL.nlev) < kLpsRowsPerLevel;
+  if (const char *e = getenv("BNX_LPS")) lps = atoi(e) != 0;  // override: 1 try it, 0 never
   SolveSys Sf, Sb;  // host copies, kept for the rank-order transforms of the block schedules
   {
     C->lps = lps && compress_both(a, split, Sf, Sb);

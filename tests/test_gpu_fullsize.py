@@ -86,15 +86,16 @@ def test_fullsize_spmv_and_ic_solves(oracle_mod, name):
         say(f"  solve {which}: fp64 {e64:.2e} fp32 {e32:.2e}")
         assert e64 < 1e-11, (which, e64)  # observed <= 5e-13 (graph), 1e-15 (diffusion, elasticity)
         assert e32 < 1e-5, (which, e32)  # observed <= 3.5e-7 on these three matrices
-    # which systems the substitutions run: FP64 the factor's own; FP32 the level-compressed ones on the grid
-    # (rows within six dependencies) and the graph (longer rows as virtual-row chains), not on elasticity
+    # which systems the substitutions run: FP64 the factor's own; FP32 the level-compressed ones on the graph
+    # (176 rows per level; its long rows as virtual-row chains), the factor's own on the grid (3356 rows per level)
+    # and on elasticity (whose substituted rows would hold 2.5x the entries)
     for prec in (FP64, MIXED):
         _, _, st = S.solve(1, precision=prec, itmax=1, tol_dacg=0.5)
         assert (st["levels_L"], st["levels_Lt"]) == LEVELS[name][prec], (name, prec)
     S.close()
 
 
-LEVELS = {"diffusion3d_100": {FP64: (298, 298), MIXED: (150, 150)},
+LEVELS = {"diffusion3d_100": {FP64: (298, 298), MIXED: (298, 298)},
           "elasticity_50": {FP64: (1041, 1041), MIXED: (1041, 1041)},
           "rgg_500k": {FP64: (2835, 2835), MIXED: (1418, 1418)}}
 
@@ -113,8 +114,8 @@ def test_fullsize_diffusion100_solve_matches_oracle():
         ev, V, st = S.solve(p, precision=prec, x0=x0)
         ev = ev.numpy()
         assert st["status"] == 0 and all(st["converged"][:p])
-        # FP32 substitutions run the level-compressed systems (298 -> 150 levels), FP64 the factor's own
-        assert (st["levels_L"], st["levels_Lt"]) == ((298, 298) if prec == FP64 else (150, 150))
+        # both precisions substitute with the factor's own systems on this grid (3356 rows per level)
+        assert (st["levels_L"], st["levels_Lt"]) == (298, 298)
         # both sides stop at ||r|| <= 1e-8 theta; the eigenvalue error is then O(||r||^2 / gap), far below 1e-10
         rel = np.abs(ev - ref) / ref
         say("  max rel eigenvalue difference vs oracle", rel.max())
