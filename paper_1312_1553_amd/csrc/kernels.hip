@@ -382,12 +382,8 @@ __global__ void k_sentinel(size_t n, T *x, int *counter, const int *gate) {
 }
 
 constexpr int kSpinLimit = 1 << 20;
-// Block solve: s_sleep of a compute wave after a polling round without progress
-// (0: none), s_wakeup of the workgroup after a round that stored values, compute
+// Block solve: s_wakeup of the workgroup after a round that stored values, compute
 // and importer waves per workgroup (the rest publish), s_sleep of a publisher poll.
-#ifndef BNX_TRSV_SLEEP
-#define BNX_TRSV_SLEEP 0
-#endif
 #ifndef BNX_TRSV_WC
 #define BNX_TRSV_WC 10
 #endif
@@ -706,35 +702,33 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     // lane 0 always holds a row of the slice; its flag tells whether any row is long (schedules
     // without long rows run the instantiation that has no general path)
     if (!LONG || (__builtin_amdgcn_readfirstlane(cur.cnt) & kLongSlice) == 0) {
-      // every row of the slice has at most NR dependencies (unused ones read the
-      // zero slot): read all NR values each round, finish when none is a sentinel
+      // every row of the slice has at most NR dependencies (unused ones read the zero slot).  Each
+      // round every lane reads its NR values (finished lanes too: their addresses are valid), the rows
+      // whose values are all in store their result, and the wave leaves once no lane is pending.  The
+      // round keeps scalar work (exec-mask changes, counters) to a minimum: the 16 waves of a
+      // workgroup share the CU's scalar unit.
       int spins = 0;
-      while (__builtin_amdgcn_ballot_w64(!fin) != 0ull) {
-        const bool fin0 = fin;
-        if (!fin) {
-          U u[NR];
+      for (;;) {
+        U u[NR];
 #pragma unroll
-          for (int q = 0; q < NR; q++)
-            u[q] = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          bool ok = true;
+        for (int q = 0; q < NR; q++)
+          u[q] = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        bool ok = true;
 #pragma unroll
-          for (int q = 0; q < NR; q++) ok = ok && u[q] != Sentinel<T>::bits;
-          if (ok) {
-            T acc = s0;
+        for (int q = 0; q < NR; q++) ok = ok && u[q] != Sentinel<T>::bits;
+        T acc = s0;
 #pragma unroll
-            for (int q = 0; q < NR; q++) acc -= cur.vv[q] * from_bits<T>(u[q]);
-            __hip_atomic_store(&xs[t], to_bits<T>(acc * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            fin = true;
-          }
-        }
-        if (++spins > kSpinLimit && !fin) {
-          __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
-          atomicOr(err, 1);
-          fin = true;
-        }
-        if (BNX_TRSV_SLEEP > 0 && __builtin_amdgcn_ballot_w64(fin != fin0) == 0ull)
-          __builtin_amdgcn_s_sleep(BNX_TRSV_SLEEP);
+        for (int q = 0; q < NR; q++) acc -= cur.vv[q] * from_bits<T>(u[q]);
+        if (ok && !fin)
+          __hip_atomic_store(&xs[t], to_bits<T>(acc * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        fin = fin || ok;
+        // both exits are wave-uniform (a ballot, a scalar counter): no exec-mask bookkeeping per round
+        if (__builtin_amdgcn_ballot_w64(!fin) == 0ull) break;
+        if (++spins > kSpinLimit) break;
+      }
+      if (!fin) {  // the bounded wait ran out
+        __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        atomicOr(err, 1);
       }
       return;
     }
