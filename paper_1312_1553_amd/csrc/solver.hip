@@ -665,12 +665,13 @@ __global__ __launch_bounds__(kBlock) void k_dacg_scale(int n, const DevCtl *c, T
 
 // Scale the iterate (x = x' inv, Ax = Ax' inv when inv != 0: the norm of x' comes from the previous step),
 // g = Ax - q x with the scale-invariant q = x'^T A x' / x'^T x'; dot g^T g.
+// Dots g^T g, x^T x, x^T A x of the scaled iterate.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T *x, T *Ax, T *g, double *part) {
   if (c->ddone) return;
   const T inv = (T)c->dinv;
   const T q = (T)c->dq;
-  T acc[1] = {T(0)};
+  T acc[3] = {T(0), T(0), T(0)};
   GRIDLOOP(i, n) {
     T xi = x[i], ai = Ax[i];
     if (inv != T(0)) {
@@ -682,16 +683,24 @@ __global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T 
     const T gi = ai - q * xi;
     g[i] = gi;
     acc[0] += gi * gi;
+    acc[1] += xi * xi;
+    acc[2] += xi * ai;
   }
-  bpart<T, 1>(acc, 1, part);
+  bpart<T, 3>(acc, 3, part);
 }
 
-// convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host
-__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag) {
+// convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host.
+// With fresh set (the FP64 iteration), x^T x and x^T A x of the stored iterate come along for this
+// iteration's line search; the FP32 iteration keeps those of its step kernel.
+__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag, int fresh) {
   if (c->ddone) return;
-  __shared__ double red[1];
-  reduce_parts(part, nb, 1, red);
+  __shared__ double red[3];
+  reduce_parts(part, nb, 3, red);
   if (threadIdx.x) return;
+  if (fresh) {
+    c->dxx = red[1];
+    c->dxAx = red[2];
+  }
   c->dgn = sqrt(red[0] / c->dxx);
   if (c->dgn < 0.9 * c->dbest) {
     c->dbest = c->dgn;
@@ -734,7 +743,7 @@ __global__ void c_dacg_beta(DevCtl *c, const double *part, int nb, int nq) {
 }
 
 // after the d update (dots d^T Ax, d^T x, d^T d) and SpMV Ad = A d (dot d^T Ad)
-__global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const double *part_d, int nbd) {
+__global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const double *part_d, int nbd, int fused) {
   if (c->ddone) return;
   __shared__ double red[1];
   __shared__ double rd[3];
@@ -758,7 +767,42 @@ __global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const dou
   }
   const double q1 = (xAx + 2 * r1 * bA + r1 * r1 * dAd) / (xx + 2 * r1 * xd + r1 * r1 * dd);
   const double q2 = (xAx + 2 * r2 * bA + r2 * r2 * dAd) / (xx + 2 * r2 * xd + r2 * r2 * dd);
-  c->dalpha = (q2 < q1) ? r2 : r1;
+  const double a = (q2 < q1) ? r2 : r1;
+  c->dalpha = a;
+  if (!fused) return;
+  // the next iterate x + a d: its squared norm and x^T A x from this step's dots, all taken on the stored
+  // vectors (equal in exact arithmetic to the dots of the updated ones, nothing carried over from earlier
+  // steps); k_dacg_move scales it to unit norm with them
+  const double nxx = xx + 2 * a * xd + a * a * dd, nxAx = xAx + 2 * a * bA + a * a * dAd;
+  const double inv = 1.0 / sqrt(nxx);
+  c->dinv = inv;
+  c->dq = nxAx / nxx;
+  c->dxx = nxx * inv * inv;
+  c->dxAx = nxAx * inv * inv;
+  c->dgamma_prev = c->dgamma;
+  c->dits++;
+}
+
+// x' = (x + a d) inv, Ax' = (Ax + a Ad) inv (inv and q from c_dacg_alpha), g = Ax' - q x'; dots g^T g,
+// x'^T x', x'^T A x'.  FP64 only: in FP32 the quotient of the unrounded step differs from that of the stored
+// vectors by about the float epsilon times ||A||, which would put a floor under ||g||
+__global__ __launch_bounds__(kBlock) void k_dacg_move(int n, const DevCtl *c, double *x, double *Ax, const double *d,
+                                                      const double *Ad, double *g, double *part) {
+  if (c->ddone) return;
+  const double a = c->dalpha, inv = c->dinv, q = c->dq;
+  double acc[3] = {0.0, 0.0, 0.0};
+  GRIDLOOP(i, n) {
+    const double xi = (x[i] + a * d[i]) * inv;
+    const double ai = (Ax[i] + a * Ad[i]) * inv;
+    x[i] = xi;
+    Ax[i] = ai;
+    const double gi = ai - q * xi;
+    g[i] = gi;
+    acc[0] += gi * gi;
+    acc[1] += xi * xi;
+    acc[2] += xi * ai;
+  }
+  bpart<double, 3>(acc, 3, part);
 }
 
 // x' = x + a d, Ax' = Ax + a Ad; dots x'^T x', x'^T A x'
@@ -1485,11 +1529,13 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   // dots of the starting vector (no scaling: inv = 0)
   hipLaunchKernelGGL((k_dacg_scale<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, area(L, 0));
   hipLaunchKernelGGL(c_dacg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbi);
+  // the first gradient (the start vector is already normalised: inv = 0 leaves it as it is)
+  hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
   Poll poll(C);
   int it;
   for (it = 0; it <= itmax; it++) {
-    hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
-    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag());
+    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag(),
+                       sizeof(T) == 8 ? 1 : 0);
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
@@ -1500,9 +1546,17 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     // (dots of the new d with Ax, x and d itself)
     int nbc = comb<T>(C, w.d, w.c0, -1.0, nullptr, w.d, &c->beta, nq, Qt, c->zQ, 1.0, 3, lx, area(L, 9), gate);
     int nbs = launch_spmv<T>(L, A, w.d, w.Ad, 1, ly, 0, VList<T>{}, area(L, 4), gate);
-    hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs, area(L, 9), nbc);
-    hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, area(L, 5));
-    hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
+    hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs, area(L, 9), nbc,
+                       sizeof(T) == 8 ? 1 : 0);
+    if constexpr (sizeof(T) == 8) {  // step, rescale and the next gradient in one pass
+      hipLaunchKernelGGL(k_dacg_move, dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, w.dg,
+                         area(L, 1));
+    } else {
+      hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad,
+                         area(L, 5));
+      hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
+      hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
+    }
     poll.post();
     if (it > 0 && poll.read_prev()) break;
   }
