@@ -384,8 +384,13 @@ __global__ void k_sentinel(size_t n, T *x, int *counter, const int *gate) {
 constexpr int kSpinLimit = 1 << 20;
 // Block solve: s_wakeup of the workgroup after a round that stored values, compute
 // and importer waves per workgroup (the rest publish), s_sleep of a publisher poll.
-#ifndef BNX_TRSV_WC
-#define BNX_TRSV_WC 10
+// compute waves per workgroup of the block solve, per precision (the rest import and publish): measured on the
+// 100^3 grid's schedules (fp64 blocks of about 4k rows, fp32 about 8k) with 4, 6, 8, 10 and 12
+#ifndef BNX_TRSV_WC64
+#define BNX_TRSV_WC64 6
+#endif
+#ifndef BNX_TRSV_WC32
+#define BNX_TRSV_WC32 8
 #endif
 #ifndef BNX_TRSV_WAKE
 #define BNX_TRSV_WAKE 0
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   }
   if (gate && *gate) return;
   T *xe = xe_pair + (size_t)par * nexp_half;
-  constexpr int WC = BNX_TRSV_WC, WI = BNX_TRSV_WI;
+  constexpr int WC = sizeof(T) == 8 ? BNX_TRSV_WC64 : BNX_TRSV_WC32, WI = BNX_TRSV_WI;
   constexpr int WP = 16 - WC - WI;
   static_assert(WP >= 1 && WI >= 1, "wave roles");
   __shared__ U xs[CAP];
