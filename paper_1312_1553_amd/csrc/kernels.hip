@@ -382,10 +382,9 @@ __global__ void k_sentinel(size_t n, T *x, int *counter, const int *gate) {
 }
 
 constexpr int kSpinLimit = 1 << 20;
-// Block solve: s_wakeup of the workgroup after a round that stored values, compute
-// and importer waves per workgroup (the rest publish), s_sleep of a publisher poll.
-// compute waves per workgroup of the block solve, per precision (the rest import and publish): measured on the
-// 100^3 grid's schedules (fp64 blocks of about 4k rows, fp32 about 8k) with 4, 6, 8, 10 and 12
+// Block solve: compute waves per workgroup per precision, importer waves, the rest publish (measured on the
+// 100^3 grid's schedules, fp64 blocks of about 4k rows and fp32 about 8k: 4 to 12 compute waves, 1 to 4
+// importers); s_wakeup of the workgroup after a round that stored values; s_sleep of a publisher poll.
 #ifndef BNX_TRSV_WC64
 #define BNX_TRSV_WC64 6
 #endif
@@ -396,7 +395,7 @@ constexpr int kSpinLimit = 1 << 20;
 #define BNX_TRSV_WAKE 0
 #endif
 #ifndef BNX_TRSV_WI
-#define BNX_TRSV_WI 2
+#define BNX_TRSV_WI 3
 #endif
 #ifndef BNX_TRSV_KC32
 #define BNX_TRSV_KC32 8
