@@ -129,6 +129,15 @@ def host_cpu():
                 mhz = float(v)
     except (OSError, ValueError):
         pass
+    if mhz is None:  # lscpu of some virtual machines shows no clock: the kernel's current figure instead
+        try:
+            for ln in open("/proc/cpuinfo"):
+                k, _, v = ln.partition(":")
+                if k.strip() == "cpu MHz":
+                    mhz = float(v)
+                    break
+        except (OSError, ValueError):
+            pass
     return {"model": model, "mhz": mhz, "nproc": os.cpu_count()}
 
 
