@@ -535,7 +535,8 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
   if (blk >= F.nblocks) return;
   const int k0 = F.bptr[blk], nrow = F.brows[blk];
   const int i0 = F.iptr[blk], nimp = F.iptr[blk + 1] - i0;
-  // LDS: rows [0, nrow), imports [nrow, nrow + nimp), the zero slot, then the right-hand side of the rows
+  // LDS: rows [0, nrow), imports [nrow, nrow + nimp), the zero slot, the right-hand side of the rows, then
+  // a dump slot that lanes past the last row write to
   const int rb = nrow + nimp + 1;
   for (int i = threadIdx.x; i <= nrow + nimp; i += 1024) xs[i] = i < nrow + nimp ? Sentinel<T>::bits : U(0);
   // right-hand side of the block's ranks (0 for a virtual row), PU ranks per thread whose loads are
@@ -707,30 +708,37 @@ __global__ __launch_bounds__(1024) void k_trsv_blk(DevBlk<T> F, const T *__restr
     // without long rows run the instantiation that has no general path)
     if (!LONG || (__builtin_amdgcn_readfirstlane(cur.cnt) & kLongSlice) == 0) {
       // every row of the slice has at most NR dependencies (unused ones read the zero slot).  Each
-      // round every lane reads its NR values (finished lanes too: their addresses are valid), the rows
-      // whose values are all in store their result, and the wave leaves once no lane is pending.  The
-      // round keeps scalar work (exec-mask changes, counters) to a minimum: the 16 waves of a
-      // workgroup share the CU's scalar unit.
-      int spins = 0;
+      // round every lane reads its NR values (finished lanes too: their addresses are valid) and stores
+      // one word: its value once all NR are in, else the sentinel again.  A finished row rewrites the
+      // same bits (its inputs no longer change), and a lane past the block writes a dump slot behind
+      // the right-hand side.  The sentinel test looks only at the high 32 bits of a double: they are
+      // those of a signalling NaN, which no arithmetic result, and hence no stored value, has.  Per
+      // round that leaves two wave-uniform exits and no exec-mask work: the 16 waves of a workgroup
+      // share the CU's scalar unit.
+      constexpr unsigned SH = (unsigned)(Sentinel<T>::bits >> (8 * sizeof(U) - 32));
+      const int dst = t < nrow ? t : rb + nrow;
+      unsigned pend = fin ? 0u : 1u;
+      int left = kSpinLimit;
       for (;;) {
         U u[NR];
 #pragma unroll
         for (int q = 0; q < NR; q++)
           u[q] = __hip_atomic_load(&xs[-cur.rr[q] - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        bool ok = true;
-#pragma unroll
-        for (int q = 0; q < NR; q++) ok = ok && u[q] != Sentinel<T>::bits;
+        unsigned m = 0xffffffffu;  // zero iff a dependency still holds the sentinel
         T acc = s0;
 #pragma unroll
-        for (int q = 0; q < NR; q++) acc -= cur.vv[q] * from_bits<T>(u[q]);
-        if (ok && !fin)
-          __hip_atomic_store(&xs[t], to_bits<T>(acc * cur.d), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        fin = fin || ok;
-        // both exits are wave-uniform (a ballot, a scalar counter): no exec-mask bookkeeping per round
-        if (__builtin_amdgcn_ballot_w64(!fin) == 0ull) break;
-        if (++spins > kSpinLimit) break;
+        for (int q = 0; q < NR; q++) {
+          const unsigned hi = (unsigned)(u[q] >> (8 * sizeof(U) - 32));
+          m = min(m, hi ^ SH);
+          acc -= cur.vv[q] * from_bits<T>(u[q]);
+        }
+        const U w = m != 0u ? to_bits<T>(acc * cur.d) : Sentinel<T>::bits;
+        __hip_atomic_store(&xs[dst], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        pend = m != 0u ? 0u : pend;
+        if (__builtin_amdgcn_ballot_w64(pend != 0u) == 0ull) break;
+        if (--left == 0) break;
       }
-      if (!fin) {  // the bounded wait ran out
+      if (pend) {  // the bounded wait ran out
         __hip_atomic_store(&xs[t], to_bits<T>(T(__builtin_nan(""))), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         atomicOr(err, 1);
       }

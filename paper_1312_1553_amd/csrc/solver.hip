@@ -2443,9 +2443,9 @@ void build_tri(bnx_ctx *C, const Analysis &a) {
     for (int dir = 0; dir < 2; dir++) {
       BlockSched bs;
       block_schedule(sa, dir == 0, prow, pstart, bs, split, nr);
-      int need = 0;  // rows + imports + zero slot + right-hand side of the rows
+      int need = 0;  // rows + imports + zero slot + right-hand side of the rows + a dump slot
       for (int q = 0; q < bs.nblocks; q++)
-        need = std::max(need, 2 * bs.brows[q] + (bs.iptr[q + 1] - bs.iptr[q]) + 1);
+        need = std::max(need, 2 * bs.brows[q] + (bs.iptr[q + 1] - bs.iptr[q]) + 2);
       if (bs.max_lds > lds || need > lds) throw ApiError{BNX_E_STATE, "block schedule exceeds LDS"};
       auto &b = C->blk[dir][pr];
       b.n = bs.n;
