@@ -348,9 +348,9 @@ __global__ void c_pcg_q(DevCtl *c, const double *part, int nb) {
 // exit tests (Sec. 4.3) and, when continuing, first-loop coefficients
 // Exit tests of the PCG iteration; posts the done flag of the iteration to the host (also when an earlier
 // step of the iteration already ended the solve).
-__global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag) {
+__global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag, int seq) {
   if (c->done) {
-    if (threadIdx.x == 0) post_flag(hflag, 1);
+    if (threadIdx.x == 0) post_flag(hflag, 2 * seq + 1);
     return;
   }
   __shared__ double red[1];
@@ -366,10 +366,10 @@ __global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag) {
   if (why >= 0) {
     c->done = 1;
     c->reason = why;
-    post_flag(hflag, 1);
+    post_flag(hflag, 2 * seq + 1);
     return;
   }
-  post_flag(hflag, 0);
+  post_flag(hflag, 2 * seq);
   first_loop(c);
 }
 
@@ -692,8 +692,11 @@ __global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T 
 // convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host.
 // With fresh set (the FP64 iteration), x^T x and x^T A x of the stored iterate come along for this
 // iteration's line search; the FP32 iteration keeps those of its step kernel.
-__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag, int fresh) {
-  if (c->ddone) return;
+__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag, int seq, int fresh) {
+  if (c->ddone) {
+    if (threadIdx.x == 0) post_flag(hflag, 2 * seq + 1);
+    return;
+  }
   __shared__ double red[3];
   reduce_parts(part, nb, 3, red);
   if (threadIdx.x) return;
@@ -711,7 +714,7 @@ __global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag, i
   const bool stall = c->dstall > 0 && c->dits - c->dbest_it >= c->dstall && c->dbest <= 10.0 * c->dtol * c->dq;
   if (stall) c->dstalled = 1;
   if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax || stall) c->ddone = 1;
-  post_flag(hflag, c->ddone);
+  post_flag(hflag, 2 * seq + c->ddone);
 }
 
 __global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
@@ -1346,28 +1349,26 @@ void free_work(bnx_ctx *C, Work<T> &w) {
 // into pinned host memory (slot l mod 2) and an event follows the iteration; the host reads iteration
 // l-1's flag while iteration l is queued.
 struct Poll {
+  // Iteration flags: the device posts 2 seq + done into pinned host memory (seq numbers the iterations
+  // from 1; done sticks once set), and the host, after queueing iteration seq, waits for the flag of
+  // iteration seq - 1 by reading that memory.  No event sits in the stream between the kernels.
   bnx_ctx *C;
-  hipEvent_t ev[2];
-  int slot = 0;
-  explicit Poll(bnx_ctx *c) : C(c) {
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    C->hflag[0] = C->hflag[1] = 0;
-  }
-  ~Poll() {
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-  }
-  int *flag() const { return C->dhflag + slot; }  // where the current iteration posts its flag
-  void post() {
-    HIPCHK(hipEventRecord(ev[slot], C->st));
-    slot ^= 1;
-  }
-  // the flag posted before the last post
-  int read_prev() {
-    const int s = slot;
-    HIPCHK(hipEventSynchronize(ev[s]));
-    return __atomic_load_n(&C->hflag[s], __ATOMIC_ACQUIRE);
+  int seq = 0;
+  explicit Poll(bnx_ctx *c) : C(c) { __atomic_store_n(&C->hflag[0], 0, __ATOMIC_RELEASE); }
+  int *flag() const { return C->dhflag; }
+  int next() { return ++seq; }  // number of the iteration being queued
+  // done flag as of iteration s (the device has run at least that far); should the stream drain with
+  // the flag missing, the queued work failed
+  int read(int s) {
+    for (long spins = 1;; spins++) {
+      const int v = __atomic_load_n(&C->hflag[0], __ATOMIC_ACQUIRE);
+      if ((v >> 1) >= s) return v & 1;
+      if ((spins & 1023) == 0 && hipStreamQuery(C->st) == hipSuccess) {
+        const int w = __atomic_load_n(&C->hflag[0], __ATOMIC_ACQUIRE);
+        if ((w >> 1) >= s) return w & 1;
+        throw ApiError{BNX_E_STATE, "iteration flag not posted by the device"};
+      }
+    }
   }
 };
 
@@ -1452,9 +1453,9 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
                          Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
     hipLaunchKernelGGL(c_pcg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
     hipLaunchKernelGGL((k_pcg_eigres<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, s_out, t, area(L, 2));
-    hipLaunchKernelGGL(c_pcg_exit, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbi, poll.flag());
-    poll.post();
-    if (l > 0 && poll.read_prev()) break;
+    const int seq = poll.next();
+    hipLaunchKernelGGL(c_pcg_exit, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 2), nbi, poll.flag(), seq);
+    if (l > 0 && poll.read(seq - 1)) break;
   }
   DevCtl h = C->readctl();
   if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
@@ -1534,7 +1535,8 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   Poll poll(C);
   int it;
   for (it = 0; it <= itmax; it++) {
-    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag(),
+    const int seq = poll.next();
+    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag(), seq,
                        sizeof(T) == 8 ? 1 : 0);
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
@@ -1557,8 +1559,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
       hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
       hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
     }
-    poll.post();
-    if (it > 0 && poll.read_prev()) break;
+    if (it > 0 && poll.read(seq - 1)) break;
   }
   DevCtl h = C->readctl();
   if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
