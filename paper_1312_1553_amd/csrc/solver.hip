@@ -1363,9 +1363,12 @@ struct Poll {
     for (long spins = 1;; spins++) {
       const int v = __atomic_load_n(&C->hflag[0], __ATOMIC_ACQUIRE);
       if ((v >> 1) >= s) return v & 1;
-      if ((spins & 1023) == 0 && hipStreamQuery(C->st) == hipSuccess) {
+      if ((spins & 1023) == 0) {
+        const hipError_t q = hipStreamQuery(C->st);
+        if (q == hipErrorNotReady) continue;
         const int w = __atomic_load_n(&C->hflag[0], __ATOMIC_ACQUIRE);
         if ((w >> 1) >= s) return w & 1;
+        HIPCHK(q);  // a failed launch or a device fault
         throw ApiError{BNX_E_STATE, "iteration flag not posted by the device"};
       }
     }
