@@ -1,0 +1,106 @@
+// Dot reductions of the bnx library: per-block partials summed in a fixed order by one 256-thread block,
+// either in a control launch after the producer (reduce_parts) or by the producer's own last block
+// (reduce_parts_fused).
+#pragma once
+
+#include "internal.h"
+
+namespace bnx {
+
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic reduction of D partial areas (part[d*nb + b]) into out[d], in a 256-thread block.
+// A lane keeps eight independent sums so that eight loads are in flight at once (the partials were
+// just written by workgroups on every XCD and are read from far memory); the summation order
+// depends on nb only.
+__device__ inline void reduce_parts(const double *part, int nb, int D, double *out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = w; d < D; d += 4) {
+    const double *p = part + (size_t)d * nb;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = lane;
+    for (; b + 7 * 64 < nb; b += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) v[u] = p[b + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 8; u++) a[u] += v[u];
+    }
+    for (int u = 0; b < nb; b += 64, u++) a[u & 7] += p[b];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    s = wsum(s);
+    if (lane == 0) out[d] = s;
+  }
+  __syncthreads();
+}
+
+// ---- reductions fused into the producing launch (no control launch after it)
+// Each block stores its partials with device-scope stores; the grid's last block waits until every slot
+// holds its partial, sums them in the order of reduce_parts (bit-identical to the two-launch form) and
+// puts the empty mark back.  Between launches every slot of the fused area holds that mark, a signalling-NaN
+// bit pattern that no arithmetic yields (arithmetic on a NaN gives a quiet NaN).  The waiting block is
+// one of the grid's own, and every other block of the grid is resident or will be, so the wait ends; the
+// bound only turns a broken invariant into an error.  A launch with more than kNBMax blocks is never fused.
+constexpr unsigned long long kEmptyMark = 0x7FF4DEAD7FF4DEADull;
+constexpr int kFusedArea = kAreas - 1;
+constexpr int kFusedSpin = 1 << 22;
+
+// A block's partial of one dot: a plain store, or a device-scope one for a fused reduction.
+__device__ __forceinline__ void store_partial(double *slot, double v, bool dev) {
+  if (dev)
+    __hip_atomic_store((unsigned long long *)slot, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *slot = v;
+}
+
+// Returns false (in every thread) when the wait bound ran out.
+__device__ inline bool reduce_parts_fused(double *part, int nb, int D, double *out) {
+  constexpr int PL = kNBMax / 64;
+  __shared__ int bad;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int d = w; d < D; d += 4) {
+    unsigned long long *p = (unsigned long long *)(part + (size_t)d * nb);
+    unsigned long long v[PL];
+#pragma unroll
+    for (int j = 0; j < PL; j++)
+      v[j] = lane + 64 * j < nb ? __hip_atomic_load(p + lane + 64 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : 0ull;
+    for (int left = kFusedSpin;;) {
+      bool pend = false;
+#pragma unroll
+      for (int j = 0; j < PL; j++) pend = pend || (lane + 64 * j < nb && v[j] == kEmptyMark);
+      if (__ballot(pend) == 0) break;
+      if (--left == 0) {
+        if (lane == 0) bad = 1;
+        break;
+      }
+#pragma unroll
+      for (int j = 0; j < PL; j++)
+        if (lane + 64 * j < nb && v[j] == kEmptyMark)
+          v[j] = __hip_atomic_load(p + lane + 64 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // reduce_parts adds slot lane + 64 j into sum j mod 8, in increasing j
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < PL; j++)
+      if (lane + 64 * j < nb) a[j & 7] += __longlong_as_double((long long)v[j]);
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    s = wsum(s);
+    if (lane == 0) out[d] = s;
+#pragma unroll
+    for (int j = 0; j < PL; j++)
+      if (lane + 64 * j < nb) __hip_atomic_store(p + lane + 64 * j, kEmptyMark, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  return bad == 0;
+}
+
+}  // namespace bnx

@@ -23,7 +23,7 @@ constexpr int kDacgStall = 200;  // float DACG: iterations without a 10 % gain t
 // eigenpairs/s (fewer blocks slow the SpMV, more make every control kernel read more partials).
 constexpr int kNBMax = BNX_NBMAX;
 constexpr int kPartSlots = 80; // dots per partial area
-constexpr int kAreas = 10;     // partial areas
+constexpr int kAreas = 11;     // partial areas; the last is for reductions run by their producer's last block
 constexpr int kBlock = 256;
 constexpr int kProbeHopsMax = 65536;  // longest chain of the latency probes
 

@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "../../include/bnx.h"
+#include "fused.h"
 #include "internal.h"
 
 using namespace bnx;
@@ -51,38 +52,6 @@ double now_s() {
 }
 
 // ============================================================== device helpers
-template <typename T>
-__device__ __forceinline__ T wsum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Deterministic reduction of D partial areas (part[d*nb + b]) into out[d], in a 256-thread block.
-// A lane keeps eight independent sums so that eight loads are in flight at once (the partials were
-// just written by workgroups on every XCD and are read from far memory); the summation order
-// depends on nb only.
-__device__ void reduce_parts(const double *part, int nb, int D, double *out) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int d = w; d < D; d += 4) {
-    const double *p = part + (size_t)d * nb;
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int b = lane;
-    for (; b + 7 * 64 < nb; b += 8 * 64) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; u++) v[u] = p[b + 64 * u];
-#pragma unroll
-      for (int u = 0; u < 8; u++) a[u] += v[u];
-    }
-    for (int u = 0; b < nb; b += 64, u++) a[u & 7] += p[b];
-    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    s = wsum(s);
-    if (lane == 0) out[d] = s;
-  }
-  __syncthreads();
-}
-
 // Convergence flag of an iteration, written straight into pinned host memory (the host polls it after the
 // iteration's event instead of copying it).
 __device__ void post_flag(int *hflag, int v) {
@@ -90,7 +59,8 @@ __device__ void post_flag(int *hflag, int v) {
   __threadfence_system();
 }
 
-template <typename T, int MAXD>
+// DEV: store with device-scope atomic stores, for a reduction fused into the same launch
+template <typename T, int MAXD, bool DEV = false>
 __device__ __forceinline__ void bpart(T (&acc)[MAXD], int nd, double *part) {
   __shared__ double red[4][MAXD];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -102,11 +72,14 @@ __device__ __forceinline__ void bpart(T (&acc)[MAXD], int nd, double *part) {
     }
   __syncthreads();
   if (threadIdx.x < nd)
-    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] +
-                                                          red[2][threadIdx.x] + red[3][threadIdx.x];
+    store_partial(part + (size_t)threadIdx.x * gridDim.x + blockIdx.x,
+                  red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x], DEV);
 }
 
 #define GRIDLOOP(i, n) for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
+
+// puts the empty mark into every slot of the fused-reduction area
+__global__ void k_arm(unsigned long long *p, int cnt) { GRIDLOOP(i, cnt) p[i] = kEmptyMark; }
 
 // First loop of Alg. 1 in compact form: a_s for s = k-1..0.
 __device__ void first_loop(DevCtl *c) {
@@ -663,12 +636,49 @@ __global__ __launch_bounds__(kBlock) void k_dacg_scale(int n, const DevCtl *c, T
   bpart<T, 2>(acc, 2, part);
 }
 
+// Convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host.
+// Runs in the last block of the kernel that produced the dots g^T g, x^T x, x^T A x (k_dacg_grad,
+// k_dacg_move).  With fresh set (the FP64 iteration), x^T x and x^T A x of the stored iterate come along for
+// this iteration's line search; the FP32 iteration keeps those of its step kernel.
+__device__ void dacg_conv(DevCtl *c, double *part, int nb, int *hflag, int seq, int fresh) {
+  __shared__ double red[3];
+  const bool ok = reduce_parts_fused(part, nb, 3, red);
+  if (threadIdx.x) return;
+  if (!ok) {
+    c->err = 1;
+    c->ddone = 1;
+    post_flag(hflag, 2 * seq + 1);
+    return;
+  }
+  if (fresh) {
+    c->dxx = red[1];
+    c->dxAx = red[2];
+  }
+  c->dgn = sqrt(red[0] / c->dxx);
+  if (c->dgn < 0.9 * c->dbest) {
+    c->dbest = c->dgn;
+    c->dbest_it = c->dits;
+  }
+  // stall (float only): no 10 % gain for dstall iterations while within 10x of the target, i.e.
+  // at the float residual floor, which can sit above tol q when q is small against ||A||
+  const bool stall = c->dstall > 0 && c->dits - c->dbest_it >= c->dstall && c->dbest <= 10.0 * c->dtol * c->dq;
+  if (stall) c->dstalled = 1;
+  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax || stall) c->ddone = 1;
+  post_flag(hflag, 2 * seq + c->ddone);
+}
+
 // Scale the iterate (x = x' inv, Ax = Ax' inv when inv != 0: the norm of x' comes from the previous step),
 // g = Ax - q x with the scale-invariant q = x'^T A x' / x'^T x'; dot g^T g.
 // Dots g^T g, x^T x, x^T A x of the scaled iterate.
+// The convergence test of the iteration (dacg_conv) runs in the last block; with the iteration done
+// already, that block only posts the flag.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T *x, T *Ax, T *g, double *part) {
-  if (c->ddone) return;
+__global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, DevCtl *c, T *x, T *Ax, T *g, double *part, int *hflag,
+                                                      int seq, int fresh) {
+  if (c->ddone) {
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) post_flag(hflag, 2 * seq + 1);
+    return;
+  }
   const T inv = (T)c->dinv;
   const T q = (T)c->dq;
   T acc[3] = {T(0), T(0), T(0)};
@@ -686,35 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_dacg_grad(int n, const DevCtl *c, T 
     acc[1] += xi * xi;
     acc[2] += xi * ai;
   }
-  bpart<T, 3>(acc, 3, part);
-}
-
-// convergence test ||g|| <= tol q ||x|| (or the iteration cap); posts the flag of the iteration to the host.
-// With fresh set (the FP64 iteration), x^T x and x^T A x of the stored iterate come along for this
-// iteration's line search; the FP32 iteration keeps those of its step kernel.
-__global__ void c_dacg_conv(DevCtl *c, const double *part, int nb, int *hflag, int seq, int fresh) {
-  if (c->ddone) {
-    if (threadIdx.x == 0) post_flag(hflag, 2 * seq + 1);
-    return;
-  }
-  __shared__ double red[3];
-  reduce_parts(part, nb, 3, red);
-  if (threadIdx.x) return;
-  if (fresh) {
-    c->dxx = red[1];
-    c->dxAx = red[2];
-  }
-  c->dgn = sqrt(red[0] / c->dxx);
-  if (c->dgn < 0.9 * c->dbest) {
-    c->dbest = c->dgn;
-    c->dbest_it = c->dits;
-  }
-  // stall (float only): no 10 % gain for dstall iterations while within 10x of the target, i.e.
-  // at the float residual floor, which can sit above tol q when q is small against ||A||
-  const bool stall = c->dstall > 0 && c->dits - c->dbest_it >= c->dstall && c->dbest <= 10.0 * c->dtol * c->dq;
-  if (stall) c->dstalled = 1;
-  if (c->dgn <= c->dtol * c->dq || c->dits >= c->ditmax || stall) c->ddone = 1;
-  post_flag(hflag, 2 * seq + c->ddone);
+  bpart<T, 3, true>(acc, 3, part);
+  if (blockIdx.x == gridDim.x - 1) dacg_conv(c, part, gridDim.x, hflag, seq, fresh);
 }
 
 __global__ void c_dacg_q(DevCtl *c, const double *part, int nb) {
@@ -789,9 +772,12 @@ __global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const dou
 // x' = (x + a d) inv, Ax' = (Ax + a Ad) inv (inv and q from c_dacg_alpha), g = Ax' - q x'; dots g^T g,
 // x'^T x', x'^T A x'.  FP64 only: in FP32 the quotient of the unrounded step differs from that of the stored
 // vectors by about the float epsilon times ||A||, which would put a floor under ||g||
-__global__ __launch_bounds__(kBlock) void k_dacg_move(int n, const DevCtl *c, double *x, double *Ax, const double *d,
-                                                      const double *Ad, double *g, double *part) {
-  if (c->ddone) return;
+__global__ __launch_bounds__(kBlock) void k_dacg_move(int n, DevCtl *c, double *x, double *Ax, const double *d,
+                                                      const double *Ad, double *g, double *part, int *hflag, int seq) {
+  if (c->ddone) {
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) post_flag(hflag, 2 * seq + 1);
+    return;
+  }
   const double a = c->dalpha, inv = c->dinv, q = c->dq;
   double acc[3] = {0.0, 0.0, 0.0};
   GRIDLOOP(i, n) {
@@ -805,12 +791,32 @@ __global__ __launch_bounds__(kBlock) void k_dacg_move(int n, const DevCtl *c, do
     acc[1] += xi * xi;
     acc[2] += xi * ai;
   }
-  bpart<double, 3>(acc, 3, part);
+  bpart<double, 3, true>(acc, 3, part);
+  if (blockIdx.x == gridDim.x - 1) dacg_conv(c, part, gridDim.x, hflag, seq, 1);
 }
 
-// x' = x + a d, Ax' = Ax + a Ad; dots x'^T x', x'^T A x'
+// next step, in the last block of k_dacg_step: inv = 1/||x'||, q, and the dots of the scaled iterate
+__device__ void dacg_next(DevCtl *c, double *part, int nb) {
+  __shared__ double red[2];
+  const bool ok = reduce_parts_fused(part, nb, 2, red);
+  if (threadIdx.x) return;
+  if (!ok) {
+    c->err = 1;
+    c->ddone = 1;
+    return;
+  }
+  const double inv = 1.0 / sqrt(red[0]);
+  c->dinv = inv;
+  c->dq = red[1] / red[0];
+  c->dxx = red[0] * inv * inv;
+  c->dxAx = red[1] * inv * inv;
+  c->dgamma_prev = c->dgamma;
+  c->dits++;
+}
+
+// x' = x + a d, Ax' = Ax + a Ad; dots x'^T x', x'^T A x' (reduced by dacg_next in the last block)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dacg_step(int n, const DevCtl *c, T *x, T *Ax, const T *d, const T *Ad,
+__global__ __launch_bounds__(kBlock) void k_dacg_step(int n, DevCtl *c, T *x, T *Ax, const T *d, const T *Ad,
                                                       double *part) {
   if (c->ddone) return;
   const T a = (T)c->dalpha;
@@ -823,22 +829,8 @@ __global__ __launch_bounds__(kBlock) void k_dacg_step(int n, const DevCtl *c, T 
     acc[0] += xi * xi;
     acc[1] += xi * ai;
   }
-  bpart<T, 2>(acc, 2, part);
-}
-
-// next step: inv = 1/||x'||, q, and the dots of the scaled iterate
-__global__ void c_dacg_next(DevCtl *c, const double *part, int nb) {
-  if (c->ddone) return;
-  __shared__ double red[2];
-  reduce_parts(part, nb, 2, red);
-  if (threadIdx.x) return;
-  const double inv = 1.0 / sqrt(red[0]);
-  c->dinv = inv;
-  c->dq = red[1] / red[0];
-  c->dxx = red[0] * inv * inv;
-  c->dxAx = red[1] * inv * inv;
-  c->dgamma_prev = c->dgamma;
-  c->dits++;
+  bpart<T, 2, true>(acc, 2, part);
+  if (blockIdx.x == gridDim.x - 1) dacg_next(c, part, gridDim.x);
 }
 
 __global__ void c_dacg_setup(DevCtl *c, double tol, int itmax, int stall) {
@@ -1461,7 +1453,7 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     if (l > 0 && poll.read(seq - 1)) break;
   }
   DevCtl h = C->readctl();
-  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "device wait bound exceeded (triangular solve or DACG convergence reduction)"};
   *its = h.its;
   *reason = h.reason;
 }
@@ -1533,14 +1525,19 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
   // dots of the starting vector (no scaling: inv = 0)
   hipLaunchKernelGGL((k_dacg_scale<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, area(L, 0));
   hipLaunchKernelGGL(c_dacg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbi);
-  // the first gradient (the start vector is already normalised: inv = 0 leaves it as it is)
-  hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
+  // the convergence test and the FP32 step's rescale run in the last block of their producers and reduce in
+  // their own area, whose slots hold the empty mark between launches
+  double *fa = area(L, kFusedArea);
+  hipLaunchKernelGGL(k_arm, dim3(grid_for((size_t)kPartSlots * kNBMax, kNBMax)), dim3(kBlock), 0, C->st,
+                     (unsigned long long *)fa, kPartSlots * kNBMax);
   Poll poll(C);
+  // the first gradient (the start vector is already normalised: inv = 0 leaves it as it is) and the
+  // convergence test of iteration 0; the FP64 test takes x^T x and x^T A x for the line search from it
+  int seq = poll.next();
+  hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, fa, poll.flag(),
+                     seq, sizeof(T) == 8 ? 1 : 0);
   int it;
   for (it = 0; it <= itmax; it++) {
-    const int seq = poll.next();
-    hipLaunchKernelGGL(c_dacg_conv, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi, poll.flag(), seq,
-                       sizeof(T) == 8 ? 1 : 0);
     // h = (I - Qt Qt^T) P0^ g
     launch_trsv<T>(L, Lf, w.dg, w.z, 0, VList<T>{}, nullptr, gate);
     launch_trsv<T>(L, Lt, w.z, w.c0, 0, VList<T>{}, nullptr, gate);
@@ -1553,16 +1550,19 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     int nbs = launch_spmv<T>(L, A, w.d, w.Ad, 1, ly, 0, VList<T>{}, area(L, 4), gate);
     hipLaunchKernelGGL(c_dacg_alpha, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 4), nbs, area(L, 9), nbc,
                        sizeof(T) == 8 ? 1 : 0);
+    // the next iterate and gradient, with the convergence test of the next iteration
+    const int nseq = poll.next();
     if constexpr (sizeof(T) == 8) {  // step, rescale and the next gradient in one pass
-      hipLaunchKernelGGL(k_dacg_move, dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, w.dg,
-                         area(L, 1));
+      hipLaunchKernelGGL(k_dacg_move, dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, w.dg, fa,
+                         poll.flag(), nseq);
     } else {
-      hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad,
-                         area(L, 5));
-      hipLaunchKernelGGL(c_dacg_next, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 5), nbi);
-      hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, area(L, 1));
+      hipLaunchKernelGGL((k_dacg_step<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.d, w.Ad, fa);
+      hipLaunchKernelGGL((k_dacg_grad<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.x, w.Ax, w.dg, fa,
+                         poll.flag(), nseq, 0);
     }
+    // the test that gated the previous iteration: the device then still has about two iterations queued
     if (it > 0 && poll.read(seq - 1)) break;
+    seq = nseq;
   }
   DevCtl h = C->readctl();
   if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
