@@ -268,7 +268,9 @@ int launch_multidot(const Launch &L, int n, int D, const VList<T> &X, const VLis
 // Dots of one or two vectors A_a (a < NAV) with a list V (nv vectors), and of A_0 with A_1 (ab = 1):
 //   part[a*nv + d] = sum_i A_a[i] V_d[i],   part[NAV*nv] = sum_i A_0[i] A_1[i]
 // Every vector is read once per element (the generic multi-dot reads a vector once per dot it appears in).
-template <typename T, typename Acc, int NAV, int MAXV>
+// RW rows per thread (a grid stride apart) have their loads in flight together; each accumulator still adds
+// the rows in grid-stride order, so the partials do not depend on RW.
+template <typename T, typename Acc, int NAV, int MAXV, int RW>
 __global__ __launch_bounds__(kBlock) void k_mdot_list(int n, const T *__restrict__ A0, const T *__restrict__ A1, int nv,
                                                       VList<T> V, int ab, double *part, const int *gate) {
   if (gate && *gate) return;
@@ -276,17 +278,28 @@ __global__ __launch_bounds__(kBlock) void k_mdot_list(int n, const T *__restrict
   Acc acc[NA];
 #pragma unroll
   for (int j = 0; j < NA; j++) acc[j] = Acc(0);
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const Acc a0 = (Acc)A0[i];
-    const Acc a1 = NAV > 1 ? (Acc)A1[i] : Acc(0);
+  const int stride = gridDim.x * kBlock;
+  for (int i0 = blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += RW * stride) {
+    Acc a0[RW], a1[RW], vv[RW][MAXV];
 #pragma unroll
-    for (int d = 0; d < MAXV; d++)
-      if (d < nv) {
-        const Acc v = (Acc)V.p[d][i];
-        acc[d] += a0 * v;
-        if (NAV > 1) acc[MAXV * (NAV - 1) + d] += a1 * v;
-      }
-    if (NAV > 1) acc[NAV * MAXV] += a0 * a1;
+    for (int u = 0; u < RW; u++) {
+      const int i = i0 + u * stride < n ? i0 + u * stride : i0;
+      a0[u] = (Acc)A0[i];
+      a1[u] = NAV > 1 ? (Acc)A1[i] : Acc(0);
+#pragma unroll
+      for (int d = 0; d < MAXV; d++) vv[u][d] = d < nv ? (Acc)V.p[d][i] : Acc(0);
+    }
+#pragma unroll
+    for (int u = 0; u < RW; u++) {
+      if (i0 + u * stride >= n) break;
+#pragma unroll
+      for (int d = 0; d < MAXV; d++)
+        if (d < nv) {
+          acc[d] += a0[u] * vv[u][d];
+          if (NAV > 1) acc[MAXV * (NAV - 1) + d] += a1[u] * vv[u][d];
+        }
+      if (NAV > 1) acc[NAV * MAXV] += a0[u] * a1[u];
+    }
   }
   // slot j < NAV*MAXV holds A_{j / MAXV}^T V_{j % MAXV}; slot NAV*MAXV holds A_0^T A_1
   auto out_of = [&](int j) {
@@ -317,15 +330,19 @@ template <typename T, typename Acc>
 int launch_mdot_list(const Launch &L, int n, int na, const T *A0, const T *A1, int nv, const VList<T> &V, int ab,
                      double *part, const int *gate) {
   const int nb = grid_for((size_t)n, L.nb);
-#define BNX_MDL(NAV, MV)                                                                                            \
-  hipLaunchKernelGGL((k_mdot_list<T, Acc, NAV, MV>), dim3(nb), dim3(kBlock), 0, L.st, n, A0, A1, nv, V, ab, part, \
-                     gate)
+  // two rows per thread while their loads fit in registers without lowering the occupancy the grid needs
+  // (four waves per SIMD): up to 64 bytes of V per row (fp64 nv <= 8: 10.8 -> 9.5 us at nv <= 4; fp32 nv <= 12:
+  // 16.5 -> 12.6 us); more (fp64 nv <= 12 took 178 VGPRs) gains nothing
+#define BNX_MDL(NAV, MV)                                                                                          \
+  hipLaunchKernelGGL((k_mdot_list<T, Acc, NAV, MV, ((MV) * sizeof(Acc) <= 64 ? 2 : 1)>), dim3(nb), dim3(kBlock), 0, \
+                     L.st, n, A0, A1, nv, V, ab, part, gate)
   if (na == 1) {
     if (nv <= 8) BNX_MDL(1, 8);
     else if (nv <= 24) BNX_MDL(1, 24);
     else BNX_MDL(1, kMaxQ + kMaxK + 1);
   } else {
     if (nv <= 4) BNX_MDL(2, 4);
+    else if (nv <= 8) BNX_MDL(2, 8);
     else if (nv <= 12) BNX_MDL(2, 12);
     else BNX_MDL(2, kMaxQ);
   }
