@@ -133,26 +133,46 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, const DevCtl *c, c
   T acc[MAXD];
 #pragma unroll
   for (int d = 0; d < MAXD; d++) acc[d] = T(0);
-  GRIDLOOP(i, n) {
-    const T api = ap[i], pi = p[i];
-    T y = api - theta * pi;
-    for (int q = 0; q < m; q++) y -= zy[q] * Q.p[q][i];
-    const T si = s[i] + gamma * pi;
-    const T gi = g[i] - gamma * y;
-    s[i] = si;
-    g[i] = gi;
-    acc[0] += gi * gi;
-    if (eig) {
-      const T ti = t[i] + gamma * api;
-      t[i] = ti;
-      const T xi = u[i] + si;
-      acc[1] += xi * (Au[i] + ti);
-      acc[2] += xi * xi;
+  // two rows a grid stride apart per pass (loads of both in flight together); every sum still takes the
+  // rows in grid-stride order
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
+    const bool two = i0 + stride < n;
+    const int ii[2] = {i0, two ? i0 + stride : i0};
+    T y[2], gi[2], si[2], api[2];
+#pragma unroll
+    for (int u2 = 0; u2 < 2; u2++) {
+      api[u2] = ap[ii[u2]];
+      const T pi = p[ii[u2]];
+      y[u2] = api[u2] - theta * pi;
+      si[u2] = s[ii[u2]] + gamma * pi;
+      gi[u2] = g[ii[u2]];
+    }
+    for (int q = 0; q < m; q++) {
+      const T *qv = Q.p[q];
+      y[0] -= zy[q] * qv[ii[0]];
+      y[1] -= zy[q] * qv[ii[1]];
     }
 #pragma unroll
-    for (int d = 3; d < MAXD; d++) {
-      if (d < 3 + k) acc[d] += S.p[d - 3][i] * gi;
-      else if (d < 3 + k + m) acc[d] += Q.p[d - 3 - k][i] * gi;
+    for (int u2 = 0; u2 < 2; u2++) {
+      if (u2 == 1 && !two) break;
+      const int i = ii[u2];
+      gi[u2] = gi[u2] - gamma * y[u2];
+      s[i] = si[u2];
+      g[i] = gi[u2];
+      acc[0] += gi[u2] * gi[u2];
+      if (eig) {
+        const T ti = t[i] + gamma * api[u2];
+        t[i] = ti;
+        const T xi = u[i] + si[u2];
+        acc[1] += xi * (Au[i] + ti);
+        acc[2] += xi * xi;
+      }
+#pragma unroll
+      for (int d = 3; d < MAXD; d++) {
+        if (d < 3 + k) acc[d] += S.p[d - 3][i] * gi[u2];
+        else if (d < 3 + k + m) acc[d] += Q.p[d - 3 - k][i] * gi[u2];
+      }
     }
   }
   bpart<T, MAXD>(acc, 3 + k + m, part);
@@ -188,16 +208,38 @@ __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, con
   T acc[NA];
 #pragma unroll
   for (int d = 0; d < NA; d++) acc[d] = T(0);
-  GRIDLOOP(i, n) {
-    T v = c0[i];
-    for (int s = 0; s < k; s++) v -= es[s] * S.p[s][i];
-    for (int q = 0; q < m; q++) v -= zq[q] * Q.p[q][i];
-    if (with_beta) v += beta * p[i];
-    p[i] = v;
+  // two rows a grid stride apart per pass (loads of both in flight together); every sum still takes the
+  // rows in grid-stride order
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
+    const bool two = i0 + stride < n;
+    const int i1 = two ? i0 + stride : i0;
+    T v0 = c0[i0], v1 = c0[i1];
+    for (int s = 0; s < k; s++) {
+      const T *sv = S.p[s];
+      v0 -= es[s] * sv[i0];
+      v1 -= es[s] * sv[i1];
+    }
+    for (int q = 0; q < m; q++) {
+      const T *qv = Q.p[q];
+      v0 -= zq[q] * qv[i0];
+      v1 -= zq[q] * qv[i1];
+    }
+    if (with_beta) {
+      v0 += beta * p[i0];
+      v1 += beta * p[i1];
+    }
+    p[i0] = v0;
+    if (two) p[i1] = v1;
 #pragma unroll
     for (int d = 0; d < NA; d++) {
-      if (d < m && d < nd) acc[d] += Q.p[d][i] * v;
-      else if (d < nd) acc[d] += AQ.p[d - m][i] * v;
+      if (d < m && d < nd) {
+        acc[d] += Q.p[d][i0] * v0;
+        if (two) acc[d] += Q.p[d][i1] * v1;
+      } else if (d < nd) {
+        acc[d] += AQ.p[d - m][i0] * v0;
+        if (two) acc[d] += AQ.p[d - m][i1] * v1;
+      }
     }
   }
   if (MAXD > 0) bpart<T, NA>(acc, nd, part);
@@ -363,14 +405,30 @@ __global__ __launch_bounds__(kBlock) void k_comb(int n, T *out, const T *b0, dou
   T acc[MAXD > 0 ? MAXD : 1];
 #pragma unroll
   for (int d = 0; d < (MAXD > 0 ? MAXD : 1); d++) acc[d] = T(0);
-  GRIDLOOP(i, n) {
-    T v = b0 ? c0 * b0[i] : T(0);
-    if (b1) v += c1 * b1[i];
-    for (int t = 0; t < nt; t++) v += lc[t] * V.p[t][i];
-    out[i] = v;
+  // two rows a grid stride apart per pass, so that the loads of both are in flight together; the rows
+  // still enter each sum in grid-stride order.  W is read after out is stored (W may hold out).
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
+    const int i1 = i0 + stride < n ? i0 + stride : i0;
+    const bool two = i0 + stride < n;
+    T v0 = b0 ? c0 * b0[i0] : T(0), v1 = b0 ? c0 * b0[i1] : T(0);
+    if (b1) {
+      v0 += c1 * b1[i0];
+      v1 += c1 * b1[i1];
+    }
+    for (int t = 0; t < nt; t++) {
+      const T *vt = V.p[t];
+      v0 += lc[t] * vt[i0];
+      v1 += lc[t] * vt[i1];
+    }
+    out[i0] = v0;
+    if (two) out[i1] = v1;
 #pragma unroll
     for (int d = 0; d < MAXD; d++)
-      if (d < nd) acc[d] += v * W.p[d][i];
+      if (d < nd) {
+        acc[d] += v0 * W.p[d][i0];
+        if (two) acc[d] += v1 * W.p[d][i1];
+      }
   }
   if (MAXD > 0) bpart<T, (MAXD > 0 ? MAXD : 1)>(acc, nd, part);
 }
