@@ -14,27 +14,37 @@ __device__ __forceinline__ T wsum(T v) {
   return v;
 }
 
-// Deterministic reduction of D partial areas (part[d*nb + b]) into out[d], in a 256-thread block.
-// A lane keeps eight independent sums so that eight loads are in flight at once (the partials were
-// just written by workgroups on every XCD and are read from far memory); the summation order
-// depends on nb only.
+// Deterministic reduction of D partial areas (part[d*nb + b], nb <= kNBMax: the areas are sized for that)
+// into out[d], in a 256-thread block.  Lane l sums slots l + 64 j into eight sums a[j mod 8] in increasing
+// j, then adds the eight in a fixed tree, so the result depends on nb only.  The partials were just
+// written by workgroups on every XCD and are read from far memory: a wave issues all of its lanes' loads
+// of two dots together (dots d and d + 4).
+__device__ __forceinline__ double sum_slots(const double (&v)[kNBMax / 64], int lane, int nb) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kNBMax / 64; j++)
+    if (lane + 64 * j < nb) a[j & 7] += v[j];
+  return wsum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+}
+
 __device__ inline void reduce_parts(const double *part, int nb, int D, double *out) {
+  constexpr int PL = kNBMax / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int d = w; d < D; d += 4) {
-    const double *p = part + (size_t)d * nb;
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int b = lane;
-    for (; b + 7 * 64 < nb; b += 8 * 64) {
-      double v[8];
+  for (int d0 = w; d0 < D; d0 += 8) {
+    const int d1 = d0 + 4;
+    const double *p0 = part + (size_t)d0 * nb, *p1 = part + (size_t)(d1 < D ? d1 : d0) * nb;
+    double v0[PL], v1[PL];
 #pragma unroll
-      for (int u = 0; u < 8; u++) v[u] = p[b + 64 * u];
-#pragma unroll
-      for (int u = 0; u < 8; u++) a[u] += v[u];
+    for (int j = 0; j < PL; j++) {
+      v0[j] = lane + 64 * j < nb ? p0[lane + 64 * j] : 0.0;
+      v1[j] = lane + 64 * j < nb && d1 < D ? p1[lane + 64 * j] : 0.0;
     }
-    for (int u = 0; b < nb; b += 64, u++) a[u & 7] += p[b];
-    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    s = wsum(s);
-    if (lane == 0) out[d] = s;
+    const double s0 = sum_slots(v0, lane, nb);
+    const double s1 = sum_slots(v1, lane, nb);
+    if (lane == 0) {
+      out[d0] = s0;
+      if (d1 < D) out[d1] = s1;
+    }
   }
   __syncthreads();
 }
@@ -87,13 +97,11 @@ __device__ inline bool reduce_parts_fused(double *part, int nb, int D, double *o
         if (lane + 64 * j < nb && v[j] == kEmptyMark)
           v[j] = __hip_atomic_load(p + lane + 64 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // reduce_parts adds slot lane + 64 j into sum j mod 8, in increasing j
-    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // the summation of reduce_parts
+    double vd[PL];
 #pragma unroll
-    for (int j = 0; j < PL; j++)
-      if (lane + 64 * j < nb) a[j & 7] += __longlong_as_double((long long)v[j]);
-    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    s = wsum(s);
+    for (int j = 0; j < PL; j++) vd[j] = __longlong_as_double((long long)v[j]);
+    const double s = sum_slots(vd, lane, nb);
     if (lane == 0) out[d] = s;
 #pragma unroll
     for (int j = 0; j < PL; j++)
