@@ -838,16 +838,34 @@ __global__ __launch_bounds__(kBlock) void k_dacg_move(int n, DevCtl *c, double *
   }
   const double a = c->dalpha, inv = c->dinv, q = c->dq;
   double acc[3] = {0.0, 0.0, 0.0};
-  GRIDLOOP(i, n) {
-    const double xi = (x[i] + a * d[i]) * inv;
-    const double ai = (Ax[i] + a * Ad[i]) * inv;
-    x[i] = xi;
-    Ax[i] = ai;
-    const double gi = ai - q * xi;
-    g[i] = gi;
-    acc[0] += gi * gi;
-    acc[1] += xi * xi;
-    acc[2] += xi * ai;
+  // two rows a grid stride apart per pass (loads of both in flight together; fp64 13.7 -> 13.1 us, no gain
+  // in the fp32 step kernels); the sums still take the rows in grid-stride order
+  const int stride = gridDim.x * blockDim.x;
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
+    const bool two = i0 + stride < n;
+    const int ii[2] = {i0, two ? i0 + stride : i0};
+    double xv[2], av[2], dv[2], adv[2];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      xv[u] = x[ii[u]];
+      av[u] = Ax[ii[u]];
+      dv[u] = d[ii[u]];
+      adv[u] = Ad[ii[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      if (u == 1 && !two) break;
+      const int i = ii[u];
+      const double xi = (xv[u] + a * dv[u]) * inv;
+      const double ai = (av[u] + a * adv[u]) * inv;
+      x[i] = xi;
+      Ax[i] = ai;
+      const double gi = ai - q * xi;
+      g[i] = gi;
+      acc[0] += gi * gi;
+      acc[1] += xi * xi;
+      acc[2] += xi * ai;
+    }
   }
   bpart<double, 3, true>(acc, 3, part);
   if (blockIdx.x == gridDim.x - 1) dacg_conv(c, part, gridDim.x, hflag, seq, 1);
