@@ -205,6 +205,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, con
   for (int q = threadIdx.x; q < m; q += kBlock) zq[q] = (T)c->zQ[q];
   __syncthreads();
   constexpr int NA = MAXD > 0 ? MAXD : 1;
+  // Q columns kept in registers between the combination and the dots, as many as leave the four waves per
+  // SIMD the grid needs (MAXD = 2 m_max when dots are asked; six of twelve: 118 VGPRs in fp64)
+  constexpr int MQ = MAXD == 8 ? 4 : (MAXD == 24 ? 6 : 0);
   T acc[NA];
 #pragma unroll
   for (int d = 0; d < NA; d++) acc[d] = T(0);
@@ -220,7 +223,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, con
       v0 -= es[s] * sv[i0];
       v1 -= es[s] * sv[i1];
     }
-    for (int q = 0; q < m; q++) {
+    // the first MQ columns of Q stay in registers for the dots below (read once)
+    T qc0[MQ > 0 ? MQ : 1], qc1[MQ > 0 ? MQ : 1];
+#pragma unroll
+    for (int q = 0; q < MQ; q++)
+      if (q < m) {
+        qc0[q] = Q.p[q][i0];
+        qc1[q] = Q.p[q][i1];
+        v0 -= zq[q] * qc0[q];
+        v1 -= zq[q] * qc1[q];
+      }
+    for (int q = MQ; q < m; q++) {
       const T *qv = Q.p[q];
       v0 -= zq[q] * qv[i0];
       v1 -= zq[q] * qv[i1];
@@ -234,8 +247,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_newp(int n, const DevCtl *c, con
 #pragma unroll
     for (int d = 0; d < NA; d++) {
       if (d < m && d < nd) {
-        acc[d] += Q.p[d][i0] * v0;
-        if (two) acc[d] += Q.p[d][i1] * v1;
+        if (d < MQ) {
+          acc[d] += qc0[d < MQ ? d : 0] * v0;
+          if (two) acc[d] += qc1[d < MQ ? d : 0] * v1;
+        } else {
+          acc[d] += Q.p[d][i0] * v0;
+          if (two) acc[d] += Q.p[d][i1] * v1;
+        }
       } else if (d < nd) {
         acc[d] += AQ.p[d - m][i0] * v0;
         if (two) acc[d] += AQ.p[d - m][i1] * v1;
