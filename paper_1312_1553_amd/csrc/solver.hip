@@ -119,8 +119,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(int n, const DevCtl *c, dou
 }
 
 // y = ap - theta p - Q zy;  s += gamma p;  g -= gamma y;  t += gamma ap
-// dots: g^T g, [x^T (Au + t), x^T x with x = u + s], S^T g (k), Q^T g (m)
-template <typename T, int MAXD>
+// dots: g^T g, [x^T (Au + t), x^T x with x = u + s], Q^T g (m), S^T g (k)
+// RW rows a grid stride apart per pass have their loads in flight together (every sum still takes the rows
+// in grid-stride order); the first MQ columns of Q stay in registers between y and the dots, so each is
+// read once (Q's dots come before the BFGS ones so that their accumulators have compile-time slots).
+template <typename T, int MAXD, int RW, int MQ>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, const DevCtl *c, const T *ap, const T *p, int m,
                                                        VList<T> Q, int k, VList<T> S, const T *u, const T *Au, T *s,
                                                        T *g, T *t, double *part) {
@@ -133,45 +136,58 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, const DevCtl *c, c
   T acc[MAXD];
 #pragma unroll
   for (int d = 0; d < MAXD; d++) acc[d] = T(0);
-  // two rows a grid stride apart per pass (loads of both in flight together); every sum still takes the
-  // rows in grid-stride order
   const int stride = gridDim.x * blockDim.x;
-  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += 2 * stride) {
-    const bool two = i0 + stride < n;
-    const int ii[2] = {i0, two ? i0 + stride : i0};
-    T y[2], gi[2], si[2], api[2];
+  for (int i0 = blockIdx.x * blockDim.x + threadIdx.x; i0 < n; i0 += RW * stride) {
+    int ii[RW];
+    bool live[RW];
 #pragma unroll
-    for (int u2 = 0; u2 < 2; u2++) {
-      api[u2] = ap[ii[u2]];
-      const T pi = p[ii[u2]];
-      y[u2] = api[u2] - theta * pi;
-      si[u2] = s[ii[u2]] + gamma * pi;
-      gi[u2] = g[ii[u2]];
+    for (int r = 0; r < RW; r++) {
+      live[r] = i0 + r * stride < n;
+      ii[r] = live[r] ? i0 + r * stride : i0;
     }
-    for (int q = 0; q < m; q++) {
+    T y[RW], gi[RW], si[RW], api[RW];
+    T qc[RW][MQ > 0 ? MQ : 1];
+#pragma unroll
+    for (int r = 0; r < RW; r++) {
+      api[r] = ap[ii[r]];
+      const T pi = p[ii[r]];
+      y[r] = api[r] - theta * pi;
+      si[r] = s[ii[r]] + gamma * pi;
+      gi[r] = g[ii[r]];
+    }
+#pragma unroll
+    for (int q = 0; q < MQ; q++)
+      if (q < m) {
+#pragma unroll
+        for (int r = 0; r < RW; r++) {
+          qc[r][q] = Q.p[q][ii[r]];
+          y[r] -= zy[q] * qc[r][q];
+        }
+      }
+    for (int q = MQ; q < m; q++) {
       const T *qv = Q.p[q];
-      y[0] -= zy[q] * qv[ii[0]];
-      y[1] -= zy[q] * qv[ii[1]];
+#pragma unroll
+      for (int r = 0; r < RW; r++) y[r] -= zy[q] * qv[ii[r]];
     }
 #pragma unroll
-    for (int u2 = 0; u2 < 2; u2++) {
-      if (u2 == 1 && !two) break;
-      const int i = ii[u2];
-      gi[u2] = gi[u2] - gamma * y[u2];
-      s[i] = si[u2];
-      g[i] = gi[u2];
-      acc[0] += gi[u2] * gi[u2];
+    for (int r = 0; r < RW; r++) {
+      if (!live[r]) break;
+      const int i = ii[r];
+      gi[r] = gi[r] - gamma * y[r];
+      s[i] = si[r];
+      g[i] = gi[r];
+      acc[0] += gi[r] * gi[r];
       if (eig) {
-        const T ti = t[i] + gamma * api[u2];
+        const T ti = t[i] + gamma * api[r];
         t[i] = ti;
-        const T xi = u[i] + si[u2];
+        const T xi = u[i] + si[r];
         acc[1] += xi * (Au[i] + ti);
         acc[2] += xi * xi;
       }
 #pragma unroll
       for (int d = 3; d < MAXD; d++) {
-        if (d < 3 + k) acc[d] += S.p[d - 3][i] * gi[u2];
-        else if (d < 3 + k + m) acc[d] += Q.p[d - 3 - k][i] * gi[u2];
+        if (d < 3 + m) acc[d] += (d - 3 < MQ ? qc[r][d - 3 < MQ ? d - 3 : 0] : Q.p[d - 3][i]) * gi[r];
+        else if (d < 3 + m + k) acc[d] += S.p[d - 3 - m][i] * gi[r];
       }
     }
   }
@@ -363,7 +379,7 @@ __global__ void c_pcg_gamma(DevCtl *c, const double *part_s, int nbs, const doub
   c->gamma = c->rho / pJp;
 }
 
-// after k_pcg_update: ||g||, q, sigma, Q^T g
+// after k_pcg_update: ||g||, q, Q^T g, sigma
 __global__ void c_pcg_q(DevCtl *c, const double *part, int nb) {
   if (c->done) return;
   __shared__ double red[3 + kMaxK + kMaxQ];
@@ -374,8 +390,8 @@ __global__ void c_pcg_q(DevCtl *c, const double *part, int nb) {
   c->xAx = red[1];
   c->xx = red[2];
   c->q = (c->xx > 0.0) ? red[1] / red[2] : 0.0;
-  for (int s = 0; s < k; s++) c->sig[s] = red[3 + s];
-  for (int q = 0; q < m; q++) c->Qg[q] = red[3 + k + q];
+  for (int q = 0; q < m; q++) c->Qg[q] = red[3 + q];
+  for (int s = 0; s < k; s++) c->sig[s] = red[3 + m + s];
 }
 
 // exit tests (Sec. 4.3) and, when continuing, first-loop coefficients
@@ -1532,14 +1548,16 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     int nbs = launch_spmv<T>(L, A, w.p, w.ap, 1, ly, 1, lx, area(L, 0), gate);
     hipLaunchKernelGGL(c_pcg_gamma, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 0), nbs, area(L, 8), nbi);
     if (Du <= 8)
-      hipLaunchKernelGGL((k_pcg_update<T, 8>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u, Au,
-                         s_out, w.g, t, area(L, 1));
-    else if (Du <= 24)
-      hipLaunchKernelGGL((k_pcg_update<T, 24>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u,
+      hipLaunchKernelGGL((k_pcg_update<T, 8, 2, 5>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u,
                          Au, s_out, w.g, t, area(L, 1));
+    else if (Du <= 24)
+      // fp64: one row per pass with eight Q columns in registers; fp32: two rows with six (both fit the
+      // four waves per SIMD the grid needs)
+      hipLaunchKernelGGL((k_pcg_update<T, 24, sizeof(T) == 8 ? 1 : 2, sizeof(T) == 8 ? 8 : 6>), dim3(nbi),
+                         dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m, Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
     else
-      hipLaunchKernelGGL((k_pcg_update<T, 3 + kMaxK + kMaxQ>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap, w.p, m,
-                         Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
+      hipLaunchKernelGGL((k_pcg_update<T, 3 + kMaxK + kMaxQ, 1, 0>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, w.ap,
+                         w.p, m, Q, k, S, u, Au, s_out, w.g, t, area(L, 1));
     hipLaunchKernelGGL(c_pcg_q, dim3(1), dim3(kBlock), 0, C->st, c, area(L, 1), nbi);
     hipLaunchKernelGGL((k_pcg_eigres<T>), dim3(nbi), dim3(kBlock), 0, C->st, n, c, u, Au, s_out, t, area(L, 2));
     const int seq = poll.next();
