@@ -69,8 +69,9 @@ __device__ __forceinline__ void store_partial(double *slot, double v, bool dev) 
     *slot = v;
 }
 
-// Returns false (in every thread) when the wait bound ran out.
-__device__ inline bool reduce_parts_fused(double *part, int nb, int D, double *out) {
+// Returns false (in every thread) when the wait bound ran out.  Forced inline, like the control steps that
+// call it: as a call it would make every producer kernel reserve the callee's registers (280 VGPRs).
+__device__ __forceinline__ bool reduce_parts_fused(double *part, int nb, int D, double *out) {
   constexpr int PL = kNBMax / 64;
   __shared__ int bad;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

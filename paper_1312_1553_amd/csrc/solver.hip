@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_dacg_scale(int n, const DevCtl *c, T
 // Runs in the last block of the kernel that produced the dots g^T g, x^T x, x^T A x (k_dacg_grad,
 // k_dacg_move).  With fresh set (the FP64 iteration), x^T x and x^T A x of the stored iterate come along for
 // this iteration's line search; the FP32 iteration keeps those of its step kernel.
-__device__ void dacg_conv(DevCtl *c, double *part, int nb, int *hflag, int seq, int fresh) {
+__device__ __forceinline__ void dacg_conv(DevCtl *c, double *part, int nb, int *hflag, int seq, int fresh) {
   __shared__ double red[3];
   const bool ok = reduce_parts_fused(part, nb, 3, red);
   if (threadIdx.x) return;
@@ -906,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_dacg_move(int n, DevCtl *c, double *
 }
 
 // next step, in the last block of k_dacg_step: inv = 1/||x'||, q, and the dots of the scaled iterate
-__device__ void dacg_next(DevCtl *c, double *part, int nb) {
+__device__ __forceinline__ void dacg_next(DevCtl *c, double *part, int nb) {
   __shared__ double red[2];
   const bool ok = reduce_parts_fused(part, nb, 2, red);
   if (threadIdx.x) return;
@@ -1565,7 +1565,7 @@ void pcg(bnx_ctx *C, Work<T> &w, const PcgParams &P, const T *r, int m, const VL
     if (l > 0 && poll.read(seq - 1)) break;
   }
   DevCtl h = C->readctl();
-  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "device wait bound exceeded (triangular solve or DACG convergence reduction)"};
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
   *its = h.its;
   *reason = h.reason;
 }
@@ -1677,7 +1677,7 @@ int dacg(bnx_ctx *C, Work<T> &w, int nq, const VList<T> &Qt, double tol, int itm
     seq = nseq;
   }
   DevCtl h = C->readctl();
-  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "triangular solve wait bound exceeded"};
+  if (h.err) throw ApiError{BNX_E_BREAKDOWN, "device wait bound exceeded (triangular solve or DACG reduction)"};
   // the last (gated) scale of x was skipped after convergence: x holds the scaled iterate
   *mvp += h.dits;
   if (stalled) *stalled = h.dstalled != 0;
