@@ -81,12 +81,25 @@ __device__ __forceinline__ void bpart(T (&acc)[MAXD], int nd, double *part) {
 // puts the empty mark into every slot of the fused-reduction area
 __global__ void k_arm(unsigned long long *p, int cnt) { GRIDLOOP(i, cnt) p[i] = kEmptyMark; }
 
-// First loop of Alg. 1 in compact form: a_s for s = k-1..0.
-__device__ void first_loop(DevCtl *c) {
-  for (int s = c->k - 1; s >= 0; s--) {
-    double v = c->sig[s];
-    for (int t = s + 1; t < c->k; t++) v -= c->a[t] * c->M[s * kMaxK + t];
-    c->a[s] = v / c->alpha[s];
+// The Gram quantities of the BFGS pairs that the serial recurrences of a control step read (M, the first
+// k rows; alpha), copied into LDS by the whole block first: one thread then reads LDS, not global memory, in
+// its dependent loops.  Ends with a barrier.
+struct GramLds {
+  double M[kMaxK * kMaxK], alpha[kMaxK], a[kMaxK];
+};
+__device__ __forceinline__ void stage_gram(const DevCtl *c, int k, GramLds &G) {
+  for (int i = threadIdx.x; i < k * kMaxK; i += blockDim.x) G.M[i] = c->M[i];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) G.alpha[i] = c->alpha[i];
+  __syncthreads();
+}
+
+// First loop of Alg. 1 in compact form: a_s for s = k-1..0 (sig and G in LDS).
+__device__ void first_loop(DevCtl *c, int k, const double *sig, GramLds &G) {
+  for (int s = k - 1; s >= 0; s--) {
+    double v = sig[s];
+    for (int t = s + 1; t < k; t++) v -= G.a[t] * G.M[s * kMaxK + t];
+    G.a[s] = v / G.alpha[s];
+    c->a[s] = G.a[s];
   }
 }
 
@@ -307,8 +320,10 @@ __global__ void c_pcg_qr(DevCtl *c, const double *part, int nb, int m) {
 // after k_pcg_init: g0, sigma, Q^T g, first-loop coefficients
 __global__ void c_pcg_init(DevCtl *c, const double *part, int nb) {
   __shared__ double red[1 + kMaxK + kMaxQ];
+  __shared__ GramLds G;
   const int k = c->k, m = c->m;
   reduce_parts(part, nb, 1 + k + m, red);
+  stage_gram(c, k, G);
   if (threadIdx.x) return;
   c->gn = sqrt(red[0]);
   c->g0 = c->gn;
@@ -319,29 +334,40 @@ __global__ void c_pcg_init(DevCtl *c, const double *part, int nb) {
     c->reason = 1;
     return;
   }
-  first_loop(c);
+  first_loop(c, k, red + 1, G);
 }
 
 // after the multi-dot (R^T c0 (k), Q^T c0 (m), g^T c0): second loop, CGS, rho, beta
 __global__ void c_pcg_beta(DevCtl *c, const double *part, int nb) {
   if (c->done) return;
   __shared__ double red[kMaxK + kMaxQ + 1];
+  __shared__ GramLds G;
+  __shared__ double QS[kMaxQ * kMaxK], sig[kMaxK], Qg[kMaxQ], e[kMaxK];
   const int k = c->k, m = c->m;
   reduce_parts(part, nb, k + m + 1, red);
+  for (int i = threadIdx.x; i < m * kMaxK; i += blockDim.x) QS[i] = c->QS[i];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    sig[i] = c->sig[i];
+    G.a[i] = c->a[i];
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) Qg[i] = c->Qg[i];
+  stage_gram(c, k, G);
   if (threadIdx.x) return;
   for (int s = 0; s < k; s++) {
     double v = red[s];
-    for (int t = 0; t < s; t++) v -= c->e[t] * c->M[t * kMaxK + s];
-    c->b[s] = v / c->alpha[s];
-    c->e[s] = c->a[s] + c->b[s];
+    for (int t = 0; t < s; t++) v -= e[t] * G.M[t * kMaxK + s];
+    const double b = v / G.alpha[s];
+    c->b[s] = b;
+    e[s] = G.a[s] + b;
+    c->e[s] = e[s];
   }
   double rho1 = red[k + m];  // g^T c0
-  for (int s = 0; s < k; s++) rho1 -= c->e[s] * c->sig[s];
+  for (int s = 0; s < k; s++) rho1 -= e[s] * sig[s];
   for (int q = 0; q < m; q++) {
     double z = red[k + q];
-    for (int s = 0; s < k; s++) z -= c->e[s] * c->QS[q * kMaxK + s];
+    for (int s = 0; s < k; s++) z -= e[s] * QS[q * kMaxK + s];
     c->zQ[q] = z;
-    rho1 -= z * c->Qg[q];
+    rho1 -= z * Qg[q];
   }
   if (c->first) {
     c->beta = 0.0;
@@ -403,7 +429,12 @@ __global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag, in
     return;
   }
   __shared__ double red[1];
+  __shared__ GramLds G;
+  __shared__ double sig[kMaxK];
+  const int k = c->k;
   if (c->eigtest) reduce_parts(part, nb, 1, red);
+  for (int i = threadIdx.x; i < k; i += blockDim.x) sig[i] = c->sig[i];
+  stage_gram(c, k, G);
   if (threadIdx.x) return;
   c->its++;
   c->eigres = c->eigtest ? sqrt(red[0] / c->xx) : INFINITY;
@@ -419,7 +450,7 @@ __global__ void c_pcg_exit(DevCtl *c, const double *part, int nb, int *hflag, in
     return;
   }
   post_flag(hflag, 2 * seq);
-  first_loop(c);
+  first_loop(c, k, sig, G);
 }
 
 // ============================================================== generic combination
@@ -695,7 +726,9 @@ __global__ void c_gram_rows(DevCtl *c, const double *part, int nb, int k, int ki
 // first-loop coefficients from sigma = S^T g and Q^T g (standalone preconditioner apply)
 __global__ void c_prec_a(DevCtl *c, const double *part, int nb, int k, int m) {
   __shared__ double red[kMaxK + kMaxQ];
+  __shared__ GramLds G;
   reduce_parts(part, nb, k + m, red);
+  stage_gram(c, k, G);
   if (threadIdx.x) return;
   c->k = k;
   c->m = m;
@@ -703,7 +736,7 @@ __global__ void c_prec_a(DevCtl *c, const double *part, int nb, int k, int m) {
   c->first = 1;
   for (int s = 0; s < k; s++) c->sig[s] = red[s];
   for (int q = 0; q < m; q++) c->Qg[q] = red[k + q];
-  first_loop(c);
+  first_loop(c, k, red, G);
 }
 
 // ============================================================== DACG kernels (Sec. 4.1)
