@@ -27,9 +27,11 @@ __device__ __forceinline__ double sum_slots(const double (&v)[kNBMax / 64], int 
   return wsum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
 }
 
-__device__ inline void reduce_parts(const double *part, int nb, int D, double *out) {
+// wfirst: the wave that takes dot 0 (so that two calls can run on different waves); sync: end with a barrier
+// (the second of two such calls must).
+__device__ inline void reduce_parts(const double *part, int nb, int D, double *out, int wfirst = 0, bool sync = true) {
   constexpr int PL = kNBMax / 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = ((threadIdx.x >> 6) - wfirst) & 3;
   for (int d0 = w; d0 < D; d0 += 8) {
     const int d1 = d0 + 4;
     const double *p0 = part + (size_t)d0 * nb, *p1 = part + (size_t)(d1 < D ? d1 : d0) * nb;
@@ -46,7 +48,7 @@ __device__ inline void reduce_parts(const double *part, int nb, int D, double *o
       if (d1 < D) out[d1] = s1;
     }
   }
-  __syncthreads();
+  if (sync) __syncthreads();
 }
 
 // ---- reductions fused into the producing launch (no control launch after it)

@@ -384,8 +384,8 @@ __global__ void c_pcg_gamma(DevCtl *c, const double *part_s, int nbs, const doub
   __shared__ double red[2];
   __shared__ double rq[2 * kMaxQ];
   const int m = c->m;
-  reduce_parts(part_s, nbs, 2, red);
-  reduce_parts(part_p, nbp, 2 * m, rq);
+  reduce_parts(part_s, nbs, 2, red, 0, false);  // waves 0 and 1, while the other two start on the m dots
+  reduce_parts(part_p, nbp, 2 * m, rq, 2);
   if (threadIdx.x) return;
   const double th = c->theta;
   const double pap = red[0], pp = red[1];
@@ -858,8 +858,8 @@ __global__ void c_dacg_alpha(DevCtl *c, const double *part_s, int nbs, const dou
   if (c->ddone) return;
   __shared__ double red[1];
   __shared__ double rd[3];
-  reduce_parts(part_s, nbs, 1, red);
-  reduce_parts(part_d, nbd, 3, rd);
+  reduce_parts(part_s, nbs, 1, red, 0, false);  // wave 0, while waves 1-3 take d's three dots
+  reduce_parts(part_d, nbd, 3, rd, 1);
   if (threadIdx.x) return;
   const double dAd = red[0], dAx = rd[0], xd = rd[1], dd = rd[2];
   const double xAx = c->dxAx, xx = c->dxx;
