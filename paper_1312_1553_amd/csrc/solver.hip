@@ -52,8 +52,8 @@ double now_s() {
 }
 
 // ============================================================== device helpers
-// Convergence flag of an iteration, written straight into pinned host memory (the host polls it after the
-// iteration's event instead of copying it).
+// Convergence flag of an iteration, written straight into pinned host memory, where the host reads it
+// (no copy and no event).
 __device__ void post_flag(int *hflag, int v) {
   __hip_atomic_store(hflag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __threadfence_system();
@@ -1479,10 +1479,7 @@ void free_work(bnx_ctx *C, Work<T> &w) {
 }
 
 // ------------------------------------------------------------------ lagged done-flag polling
-// The host enqueues iteration l+1 before reading the flag written by iteration l.
-// Lagged host polling of a device convergence flag: the last control step of iteration l writes the flag
-// into pinned host memory (slot l mod 2) and an event follows the iteration; the host reads iteration
-// l-1's flag while iteration l is queued.
+// The host queues an iteration before it reads the flag of an earlier one, so the device never waits for it.
 struct Poll {
   // Iteration flags: the device posts 2 seq + done into pinned host memory (seq numbers the iterations
   // from 1; done sticks once set), and the host, after queueing iteration seq, waits for the flag of
